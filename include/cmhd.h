@@ -1,0 +1,203 @@
+/*
+ * cmhd.h -- C ABI of the MI355X (gfx950) coronal MHD time step.
+ *
+ * One call of cmhd_rk3_step advances the compressible resistive MHD system in
+ * vector potential A, velocity u, ln rho and ln T by one low-storage
+ * third-order Runge-Kutta step, with the boundary set of Bourdin (2019,
+ * arXiv:1908.08557): periodic horizontal directions, a photospheric lower
+ * boundary that nudges u and A toward a driver (Sect. 2.3, eq. 5; Sect. 2.1),
+ * an inverted potential-field extrapolation below the photosphere
+ * (Sect. 2.4), density fixed to its initial profile and hydrostatic
+ * temperature ghosts (Sect. 2.5, eq. 8), a closed upper boundary with
+ * symmetric temperature and hydrostatic density (Sect. 4.1, eqs. 11-13), a
+ * potential-field upper boundary computed by 2-D Fourier transforms
+ * (Sect. 4.2, eqs. 16-17) and swamp layers (Sect. 4.3, eqs. 18-20).
+ * B = curl A in the Weyl gauge (Sect. 2.4, eqs. 6-7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout.  One device buffer of float64 holding the eight fields
+ *   Ax, Ay, Az, ux, uy, uz, ln rho, ln T (in this order), each an array
+ *   [nz+6][ny][nx] with x fastest.  Plane index kz = k + 3 holds height
+ *   z_k = z0 + k dz for k = -3 .. nz+2: three ghost planes below and above
+ *   the interior.  x and y are periodic and stored without ghosts.  The
+ *   buffer holds cmhd_state_elems() doubles.  In solar mode the planes
+ *   k = -3..-1 of ux and uy are part of the state (they evolve under the
+ *   nudging term of eq. 5 alone); every other ghost plane is derived and is
+ *   overwritten by cmhd_fill_ghosts.
+ * Units.  Whatever consistent units the caller uses; mu0, R and gamma are
+ *   parameters.
+ * Ownership.  The context is allocated by cmhd_init_grid and freed by
+ *   cmhd_destroy.  All device memory is owned by the caller: the state and
+ *   the workspace bound with cmhd_bind_workspace.  The library never frees a
+ *   caller pointer and keeps no pointer to a state buffer between calls.
+ * Streams.  Every kernel of a context runs on its stream (cmhd_set_stream);
+ *   calls return before the work completes unless stated otherwise.  A
+ *   context must not be used from two host threads at once.
+ * Errors.  Every function returns a cmhd_status; on failure
+ *   cmhd_last_error() describes the cause and no kernel was launched.
+ */
+#ifndef CMHD_H
+#define CMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CMHD_OK = 0,
+  CMHD_EINVAL = -1,      /* invalid argument (sizes, parameters, pointers) */
+  CMHD_EDEVICE = -2,     /* a HIP runtime call failed */
+  CMHD_ENONFINITE = -3,  /* a non-finite value was found (cmhd_check_finite) */
+  CMHD_ESTATE = -5,      /* call out of order (e.g. no workspace bound) */
+  CMHD_EWORKSPACE = -6   /* workspace too small */
+} cmhd_status;
+
+typedef enum { CMHD_FP64 = 0, CMHD_FP32_SPLIT = 1 } cmhd_precision;
+typedef enum { CMHD_ZBC_PERIODIC = 0, CMHD_ZBC_SOLAR = 1 } cmhd_zbc;
+
+#define CMHD_MAX_RAD 16
+
+typedef struct cmhd_ctx cmhd_ctx;
+
+/* Grid.  nx, ny: powers of two >= 8 (the Fourier boundary and the tiles need
+ * them), nz >= 7 (solar) or >= 8 (periodic), nx and ny multiples of 16.
+ * dx = Lx/nx, dy = Ly/ny.  Solar z is vertex-centred: dz = (z1-z0)/(nz-1),
+ * z_0 = z0 is the photosphere and z_{nz-1} = z1 the top boundary point (the
+ * boundary layers j = 0 of Sect. 2.3 and nz of Sect. 4.1).  Periodic z:
+ * dz = (z1-z0)/nz.
+ * prec = CMHD_FP32_SPLIT evaluates the right-hand side in float32 (stencil
+ * differences of the float64 state are formed in float64 first) while the
+ * state, the Runge-Kutta register and update, the ghost rules, the Fourier
+ * transforms and the conduction coefficient kappa0 T^5/2 stay float64. */
+typedef struct {
+  int nx, ny, nz;
+  double Lx, Ly, z0, z1;
+  int zbc;   /* cmhd_zbc */
+  int prec;  /* cmhd_precision */
+} cmhd_grid;
+
+/* Physical and numerical parameters (all in the caller's units).
+ *  gamma, R, mu0     ideal gas p = rho R T, c_v = R/(gamma-1); mu0 J = curl B
+ *  eta, nu           magnetic diffusivity, kinematic viscosity (constant)
+ *  D_rho             mass diffusivity of Sect. 2.5
+ *  kappa0            Spitzer coefficient: heat flux kappa0 T^5/2 b (b.grad T)
+ *  g_z               signed vertical gravity (negative: pointing down)
+ *  Bext              uniform field added to curl A
+ *  B_floor           |B| regularisation of the field direction b = B/|B|_r
+ *  eta_s, chi_s, chi_rho, z_s, z_t   swamp layers, eqs. (18)-(20), with the
+ *                    cubic step w(z) from z_s to z_t (Sect. 4.3)
+ *  tau_u             inverse time of the u_h nudging, eq. (5)
+ *  tau_A             inverse time of the A_h nudging at the photosphere
+ *  t_ramp            duration of the linear driver switch-on (Sect. 2.3);
+ *                    <= 0: no ramp
+ *  f_bot             contrast factor of the inverted potential field below
+ *                    the photosphere (Sect. 2.4, one fifth in the paper)
+ *  n_rad, rad_lnT, rad_lnL   optically thin loss Q = rho^2 exp(lnL(ln T))
+ *                    with lnL piecewise linear through the breakpoints and
+ *                    constant outside; n_rad = 0 switches it off
+ *  T_rad_lo, T_rad_hi smoothstep in ln T that switches the loss on
+ *  c_adv, c_diff, c_nudge   Courant factors of cmhd_cfl_dt
+ * Periodic z ignores the swamp, nudging and boundary parameters. */
+typedef struct {
+  double gamma, R, mu0, eta, nu, D_rho, kappa0, g_z;
+  double Bext[3];
+  double B_floor;
+  double eta_s, chi_s, chi_rho, z_s, z_t;
+  double tau_u, tau_A, t_ramp, f_bot;
+  int n_rad;
+  double rad_lnT[CMHD_MAX_RAD], rad_lnL[CMHD_MAX_RAD];
+  double T_rad_lo, T_rad_hi;
+  double c_adv, c_diff, c_nudge;
+} cmhd_params;
+
+/* Create a context.  lnrho0_z: host array of nz+6 doubles, the initial
+ * ln rho profile at z_k, k = -3..nz+2; its three lowest entries are the
+ * density imposed below the photosphere ('fg', Sect. 2.5) and entry 3 the
+ * photospheric value held fixed.  It is copied.  stream: a hipStream_t (NULL
+ * = the null stream).  *out receives the context.  EINVAL on bad sizes or
+ * parameters, EDEVICE when no gfx950 device is current. */
+cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
+                           const double* lnrho0_z, void* stream, cmhd_ctx** out);
+
+/* Number of doubles of one state buffer: 8*(nz+6)*ny*nx. */
+size_t cmhd_state_elems(const cmhd_ctx* ctx);
+
+/* Bytes of device workspace the context needs: two state buffers for the
+ * intermediate Runge-Kutta stages, the Runge-Kutta register, the driver
+ * targets and the Fourier scratch.  The caller allocates it (aligned to 256
+ * bytes) and binds it; it must outlive every later call. */
+size_t cmhd_workspace_bytes(const cmhd_ctx* ctx);
+cmhd_status cmhd_bind_workspace(cmhd_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Change the stream of all later launches. */
+cmhd_status cmhd_set_stream(cmhd_ctx* ctx, void* stream);
+
+/* Photospheric driver (solar mode).  uh: device [2][ny][nx], the target
+ * horizontal velocity u* of eq. (5).  Then exactly one of
+ *   ah: device [2][ny][nx], the nudging target A_h* of A_x, A_y, or
+ *   bz: device [ny][nx], a vertical field from which A_h* is computed so
+ *       that d_x A_y - d_y A_x = B_z (eq. 7) in Fourier space (mean and
+ *       Nyquist modes set to zero); EINVAL if its net flux exceeds
+ *       1e-12 * sum |B_z| (Sect. 2.1: balanced flux).
+ * may be non-NULL (both NULL keeps the previous A_h*).  The inputs are
+ * copied on the context stream; the caller may free them once that stream
+ * has passed this call. */
+cmhd_status cmhd_set_driver(cmhd_ctx* ctx, const double* uh, const double* bz,
+                            const double* ah);
+
+/* Fill every derived ghost plane of the device state in place (solar: the
+ * rules listed at the top; periodic: plane copies).  t is unused today (the
+ * rules do not depend on time) and kept for time-dependent boundaries. */
+cmhd_status cmhd_fill_ghosts(cmhd_ctx* ctx, double* state, double t);
+
+/* Advance the device state in place by one RK3 step from time *t.  dt > 0:
+ * use it; dt <= 0: compute it first with cmhd_cfl_dt (one device-to-host
+ * copy, synchronous).  On return *t has advanced by the step and *dt_used
+ * (if non-NULL) holds it.  The derived ghosts of the state are refreshed on
+ * entry and are stale on return; the interior and the ux, uy lower ghost
+ * planes hold the new state.  Needs a bound workspace (ESTATE). */
+cmhd_status cmhd_rk3_step(cmhd_ctx* ctx, double* state, double* t, double dt,
+                          double* dt_used);
+
+/* Evaluate the right-hand side once at time t: fills the derived ghosts of
+ * the state, then writes dF/dt into rhs (device, state layout and size) at
+ * every interior point and, in solar mode, at the ux, uy lower ghost rows;
+ * the other entries of rhs are left unchanged.  Needs a bound workspace. */
+cmhd_status cmhd_eval_rhs(cmhd_ctx* ctx, double* state, double t, double* rhs);
+
+/* Time step from the Courant, diffusion, radiative-cooling and nudging
+ * limits over the interior (fills the ghosts first).  Synchronous. */
+cmhd_status cmhd_cfl_dt(cmhd_ctx* ctx, double* state, double* dt_out);
+
+/* Copy the fields selected by mask (bit f = field f) to dst, packed in field
+ * order as [nsel][nz][ny][nx] (with_ghosts = 0) or [nsel][nz+6][ny][nx].
+ * dst_on_host != 0: dst is host memory and the call is synchronous. */
+cmhd_status cmhd_get_fields(cmhd_ctx* ctx, const double* state, unsigned mask,
+                            double* dst, int dst_on_host, int with_ghosts);
+
+/* B_z = d_x A_y - d_y A_x + Bext_z on the horizontal plane at height z,
+ * linear between the two enclosing grid planes, into device dst [ny][nx]. */
+cmhd_status cmhd_bz_plane(cmhd_ctx* ctx, const double* state, double z, double* dst);
+
+/* Non-zero when every interior value of the state is finite (synchronous).
+ * Returns CMHD_ENONFINITE otherwise. */
+cmhd_status cmhd_check_finite(cmhd_ctx* ctx, const double* state);
+
+/* Kernel timing.  While enabled, cmhd_rk3_step records a pair of HIP events
+ * on the context stream around every launch of the fused substage kernel.
+ * cmhd_profile_read synchronises the stream, returns the summed duration in
+ * milliseconds and the number of launches since the last read, and resets
+ * them.  Enabling and disabling keep pending records. */
+cmhd_status cmhd_profile_enable(cmhd_ctx* ctx, int enable);
+cmhd_status cmhd_profile_read(cmhd_ctx* ctx, double* ms, int* launches);
+
+const char* cmhd_last_error(const cmhd_ctx* ctx);
+void cmhd_destroy(cmhd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMHD_H */

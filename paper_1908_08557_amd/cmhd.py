@@ -1,0 +1,274 @@
+"""ctypes binding of libcmhd.so (include/cmhd.h), argument marshalling only.
+
+Device memory and streams come from PyTorch: the state is a float64 CUDA
+(ROCm) tensor of shape [8, nz+6, ny, nx], the workspace a uint8 tensor, and
+every call runs on torch's current stream.  All arithmetic of the step runs
+in the library's kernels; if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libcmhd.so")
+
+CMHD_OK, CMHD_EINVAL, CMHD_EDEVICE, CMHD_ENONFINITE = 0, -1, -2, -3
+CMHD_ESTATE, CMHD_EWORKSPACE = -5, -6
+CMHD_FP64, CMHD_FP32_SPLIT = 0, 1
+CMHD_ZBC_PERIODIC, CMHD_ZBC_SOLAR = 0, 1
+MAX_RAD = 16
+
+
+class CmhdGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("z0", ctypes.c_double), ("z1", ctypes.c_double),
+                ("zbc", ctypes.c_int), ("prec", ctypes.c_int)]
+
+
+class CmhdParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("gamma", "R", "mu0", "eta", "nu", "D_rho", "kappa0", "g_z")] + [
+        ("Bext", ctypes.c_double * 3), ("B_floor", ctypes.c_double)] + [
+        (n, ctypes.c_double) for n in
+        ("eta_s", "chi_s", "chi_rho", "z_s", "z_t", "tau_u", "tau_A", "t_ramp", "f_bot")] + [
+        ("n_rad", ctypes.c_int), ("rad_lnT", ctypes.c_double * MAX_RAD),
+        ("rad_lnL", ctypes.c_double * MAX_RAD)] + [
+        (n, ctypes.c_double) for n in ("T_rad_lo", "T_rad_hi", "c_adv", "c_diff", "c_nudge")]
+
+
+class CmhdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cmhd error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with "
+                          "`python -m paper_1908_08557_amd.build`")
+    lib = ctypes.CDLL(LIBPATH)
+    P, D, I, U, S = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
+    sig = {
+        "cmhd_init_grid": (I, [ctypes.POINTER(CmhdGrid), ctypes.POINTER(CmhdParams),
+                               ctypes.POINTER(D), P, ctypes.POINTER(P)]),
+        "cmhd_state_elems": (S, [P]),
+        "cmhd_workspace_bytes": (S, [P]),
+        "cmhd_bind_workspace": (I, [P, P, S]),
+        "cmhd_set_stream": (I, [P, P]),
+        "cmhd_set_driver": (I, [P, P, P, P]),
+        "cmhd_fill_ghosts": (I, [P, P, D]),
+        "cmhd_rk3_step": (I, [P, P, ctypes.POINTER(D), D, ctypes.POINTER(D)]),
+        "cmhd_cfl_dt": (I, [P, P, ctypes.POINTER(D)]),
+        "cmhd_eval_rhs": (I, [P, P, D, P]),
+        "cmhd_get_fields": (I, [P, P, U, P, I, I]),
+        "cmhd_bz_plane": (I, [P, P, D, P]),
+        "cmhd_check_finite": (I, [P, P]),
+        "cmhd_profile_enable": (I, [P, I]),
+        "cmhd_profile_read": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "cmhd_last_error": (ctypes.c_char_p, [P]),
+        "cmhd_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return ["cmhd_init_grid", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
+            "cmhd_set_stream", "cmhd_set_driver", "cmhd_fill_ghosts", "cmhd_rk3_step",
+            "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_bz_plane", "cmhd_check_finite",
+            "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy"]
+
+
+def make_grid(grid: dict, precision: str = "fp64") -> CmhdGrid:
+    g = CmhdGrid()
+    g.nx, g.ny, g.nz = grid["nx"], grid["ny"], grid["nz"]
+    g.Lx, g.Ly, g.z0, g.z1 = grid["Lx"], grid["Ly"], grid["z0"], grid["z1"]
+    g.zbc = CMHD_ZBC_SOLAR if grid["zbc"] == "solar" else CMHD_ZBC_PERIODIC
+    g.prec = {"fp64": CMHD_FP64, "fp32_split": CMHD_FP32_SPLIT}[precision]
+    return g
+
+
+def make_params(par: dict) -> CmhdParams:
+    p = CmhdParams()
+    for name in ("gamma", "R", "mu0", "eta", "nu", "D_rho", "kappa0", "g_z", "B_floor",
+                 "eta_s", "chi_s", "chi_rho", "z_s", "z_t", "tau_u", "tau_A", "t_ramp", "f_bot",
+                 "T_rad_lo", "T_rad_hi", "c_adv", "c_diff", "c_nudge"):
+        setattr(p, name, float(par[name]))
+    for i in range(3):
+        p.Bext[i] = float(par["Bext"][i])
+    lnT = np.asarray(par["rad_lnT"], dtype=np.float64)
+    lnL = np.asarray(par["rad_lnL"], dtype=np.float64)
+    if len(lnT) > MAX_RAD:
+        raise ValueError("radiation table too long")
+    p.n_rad = len(lnT)
+    for i in range(len(lnT)):
+        p.rad_lnT[i] = lnT[i]
+        p.rad_lnL[i] = lnL[i]
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One library context: grid, parameters, bound workspace."""
+
+    def __init__(self, grid: dict, params: dict, lnrho0_z, precision: str = "fp64",
+                 device: str = "cuda"):
+        self.lib = load()
+        self.grid = dict(grid)
+        self.params = dict(params)
+        self.precision = precision
+        self.device = torch.device(device)
+        self._g = make_grid(grid, precision)
+        self._p = make_params(params)
+        lr = np.ascontiguousarray(np.asarray(lnrho0_z, dtype=np.float64))
+        self._lr = lr
+        ctx = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.cmhd_init_grid(ctypes.byref(self._g), ctypes.byref(self._p),
+                                     lr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.c_void_p(stream), ctypes.byref(ctx))
+        if rc != CMHD_OK:
+            raise CmhdError(rc, "cmhd_init_grid failed (see stderr)")
+        self.ctx = ctx
+        nbytes = self.lib.cmhd_workspace_bytes(ctx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.cmhd_bind_workspace(ctx, ctypes.c_void_p(base + off), nbytes))
+        g = grid
+        self.state_shape = (8, g["nz"] + 6, g["ny"], g["nx"])
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, rc):
+        if rc != CMHD_OK:
+            msg = self.lib.cmhd_last_error(self.ctx).decode()
+            raise CmhdError(rc, msg)
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.cmhd_set_stream(self.ctx, ctypes.c_void_p(s)))
+
+    def _state(self, state):
+        if (state.dtype != torch.float64 or not state.is_cuda or not state.is_contiguous()
+                or tuple(state.shape) != self.state_shape):
+            raise ValueError(f"state must be a contiguous float64 device tensor {self.state_shape}")
+        return ctypes.c_void_p(state.data_ptr())
+
+    def new_state(self, host_state=None):
+        if host_state is None:
+            return torch.zeros(self.state_shape, dtype=torch.float64, device=self.device)
+        return torch.as_tensor(np.ascontiguousarray(host_state), dtype=torch.float64,
+                               device=self.device).contiguous()
+
+    # -- API ---------------------------------------------------------------------
+    def set_driver(self, uh, bz=None, ah=None):
+        self._stream()
+        dev = lambda a: None if a is None else torch.as_tensor(
+            np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+            dtype=torch.float64, device=self.device).contiguous()
+        self._drv = (dev(uh), dev(bz), dev(ah))   # kept alive until the stream passes
+        self._check(self.lib.cmhd_set_driver(self.ctx, _ptr(self._drv[0]), _ptr(self._drv[1]),
+                                             _ptr(self._drv[2])))
+
+    def fill_ghosts(self, state, t=0.0):
+        self._stream()
+        self._check(self.lib.cmhd_fill_ghosts(self.ctx, self._state(state), float(t)))
+
+    def rk3_step(self, state, t, dt):
+        self._stream()
+        tt = ctypes.c_double(t)
+        used = ctypes.c_double(0.0)
+        self._check(self.lib.cmhd_rk3_step(self.ctx, self._state(state), ctypes.byref(tt),
+                                           float(dt), ctypes.byref(used)))
+        return tt.value, used.value
+
+    def eval_rhs(self, state, t=0.0):
+        """Right-hand side dF/dt as a new device tensor in the state layout
+        (entries outside the interior and the u_h ghost rows are zero)."""
+        self._stream()
+        out = torch.zeros(self.state_shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.cmhd_eval_rhs(self.ctx, self._state(state), float(t), _ptr(out)))
+        return out
+
+    def cfl_dt(self, state):
+        self._stream()
+        dt = ctypes.c_double(0.0)
+        self._check(self.lib.cmhd_cfl_dt(self.ctx, self._state(state), ctypes.byref(dt)))
+        return dt.value
+
+    def get_fields(self, state, mask=0xFF, with_ghosts=False):
+        """Selected fields copied to a new host float64 array."""
+        self._stream()
+        nsel = bin(mask & 0xFF).count("1")
+        g = self.grid
+        nzc = g["nz"] + 6 if with_ghosts else g["nz"]
+        out = np.empty((nsel, nzc, g["ny"], g["nx"]))
+        self._check(self.lib.cmhd_get_fields(self.ctx, self._state(state), mask,
+                                             ctypes.c_void_p(out.ctypes.data), 1,
+                                             1 if with_ghosts else 0))
+        return out
+
+    def bz_plane(self, state, z, out=None):
+        self._stream()
+        if out is None:
+            out = torch.empty((self.grid["ny"], self.grid["nx"]), dtype=torch.float64,
+                              device=self.device)
+        self._check(self.lib.cmhd_bz_plane(self.ctx, self._state(state), float(z), _ptr(out)))
+        return out
+
+    def check_finite(self, state):
+        self._stream()
+        rc = self.lib.cmhd_check_finite(self.ctx, self._state(state))
+        if rc == CMHD_ENONFINITE:
+            return False
+        self._check(rc)
+        return True
+
+    def profile(self, enable=True):
+        self._check(self.lib.cmhd_profile_enable(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """(total ms, launches) of the fused substage kernel since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int(0)
+        self._check(self.lib.cmhd_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.cmhd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, precision="fp64", device="cuda"):
+    """Solver for a workloads.Workload, with its driver already set."""
+    s = Solver(workload.grid, workload.params, workload.lnrho0_z, precision, device)
+    if workload.grid["zbc"] == "solar" and workload.uh_target is not None:
+        s.set_driver(workload.uh_target, ah=workload.ah_target)
+    return s

@@ -1,0 +1,500 @@
+// Ghost planes in z and the 2-D Fourier work of the magnetic boundaries.
+//
+// Solar mode (vertex-centred z, k = 0 photosphere, k = nz-1 top):
+//   below (k = -j):  A by the inverted potential field exp(+f_bot |k| j dz)
+//                    (Sect. 2.4), u_z antisymmetric (closed, Sect. 2.5),
+//                    ln rho = initial profile ('fg'), ln T by the hydrostatic
+//                    recursion of eq. (8) read as
+//                      ln T(-j) = ln T(-j+1) + ln rho(-j+1) - ln rho(-j)
+//                                 - dz g / (R T(-j+1)),
+//                    u_x, u_y are state (not touched);
+//   above (k = nz-1+j, mirror m = nz-1-j): A by the potential field
+//                    exp(-|k| j dz) (eqs. 16-17), u_z antisymmetric, u_x, u_y
+//                    symmetric (closed, Sect. 4.1), ln T symmetric (eq. 11),
+//                    ln rho(nz-1+j) = ln rho(m) + g (z_{nz-1+j} - z_m)/(R T(nz-1))
+//                    (eq. 13 with p = rho R T).
+// Periodic mode: plane copies.
+//
+// Fourier transforms: radix-2 decimation-in-time, one workgroup per 1-D
+// transform staged in LDS (rows, then columns), float64 throughout.
+// Forward transform unnormalised, inverse normalised by 1/(nx ny) in the
+// spectral filter.  Because the multipliers are real and even in k, two real
+// planes are filtered at once as the real and imaginary parts of one complex
+// plane.
+#include "cmhd_internal.h"
+
+namespace cmhd {
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// z ghosts
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_periodic_z(const KParams p, double* __restrict__ f) {
+  const long long plane = p.splane;
+  const long long n = (long long)NF * 2 * NG * plane;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int fi = int(i / (2 * NG * plane));
+    const long long r = i - (long long)fi * 2 * NG * plane;
+    const int j = int(r / plane);          // 0..5
+    const long long col = r - (long long)j * plane;
+    double* a = f + fi * p.sfield + col;
+    if (j < NG) {
+      a[j * plane] = a[(p.nz + j) * plane];                       // below <- top of interior
+    } else {
+      const int jj = j - NG;
+      a[(p.nz + NG + jj) * plane] = a[(NG + jj) * plane];          // above <- bottom of interior
+    }
+  }
+}
+
+__global__ void k_fill_solar_columns(const KParams p, double* __restrict__ f) {
+  const long long sp = p.splane;
+  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < sp;
+       col += (long long)gridDim.x * blockDim.x) {
+    double* uz = f + UZ * p.sfield + col;
+    double* ux = f + UX * p.sfield + col;
+    double* uy = f + UY * p.sfield + col;
+    double* lr = f + LR * p.sfield + col;
+    double* lT = f + LT * p.sfield + col;
+    const int kb = NG;                 // array plane of k = 0
+    const int kt = NG + p.nz - 1;      // array plane of k = nz-1
+#pragma unroll
+    for (int j = 1; j <= NG; ++j) {
+      uz[(kb - j) * sp] = -uz[(kb + j) * sp];
+      uz[(kt + j) * sp] = -uz[(kt - j) * sp];
+      ux[(kt + j) * sp] = ux[(kt - j) * sp];
+      uy[(kt + j) * sp] = uy[(kt - j) * sp];
+      lr[(kb - j) * sp] = p.lnrho0_bot[NG - j];
+    }
+    // hydrostatic lower temperature ghosts, recursive downward
+#pragma unroll
+    for (int j = 1; j <= NG; ++j) {
+      const int up = kb - j + 1;
+      const double Tup = exp(lT[up * sp]);
+      lT[(kb - j) * sp] =
+          lT[up * sp] + lr[up * sp] - lr[(kb - j) * sp] - p.dz * p.g_z / (p.R * Tup);
+    }
+    // symmetric temperature and hydrostatic density above
+    const double Ttop = exp(lT[kt * sp]);
+#pragma unroll
+    for (int j = 1; j <= NG; ++j) {
+      lT[(kt + j) * sp] = lT[(kt - j) * sp];
+      lr[(kt + j) * sp] = lr[(kt - j) * sp] + p.g_z * (2.0 * j * p.dz) / (p.R * Ttop);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1-D FFT in LDS: one workgroup per transform, length n = 2^logn <= 1024
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// transform b: elements at base(b) + j*stride, j = 0..n-1, where
+// base(b) = (b / inner) * outer + (b % inner) * istride
+__global__ void k_fft1d(double2* __restrict__ data, int n, int logn, long long stride, int inner,
+                        long long outer, long long istride, double sign) {
+  __shared__ double2 buf[1024];
+  const long long b = blockIdx.x;
+  const long long base = (b / inner) * outer + (b % inner) * istride;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = (int)(__brev((unsigned)i) >> (32 - logn));
+    buf[r] = data[base + i * stride];
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1;
+    __syncthreads();
+    for (int t = threadIdx.x; t < (n >> 1); t += blockDim.x) {
+      const int g = t / half, pos = t - g * half;
+      const int i0 = g * len + pos, i1 = i0 + half;
+      double sn, cs;
+      sincospi(2.0 * pos / len, &sn, &cs);
+      const double2 w = make_double2(cs, sign * sn);
+      const double2 a = buf[i0];
+      const double2 bb = cmul(buf[i1], w);
+      buf[i0] = make_double2(a.x + bb.x, a.y + bb.y);
+      buf[i1] = make_double2(a.x - bb.x, a.y - bb.y);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) data[base + i * stride] = buf[i];
+}
+
+// forward (sign -1) or inverse (+1) 2-D transform of nplanes planes [ny][nx]
+hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStream_t s) {
+  const int nx = p.nx, ny = p.ny;
+  const long long plane = (long long)nx * ny;
+  const int tx = nx / 2 < 256 ? nx / 2 : 256;
+  const int ty = ny / 2 < 256 ? ny / 2 : 256;
+  // rows: transform b = (plane, row); contiguous
+  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * ny), dim3(tx), 0, s, d, nx, ilog2(nx), 1LL, 1,
+                     (long long)nx, 0LL, sign);
+  // columns: transform b = (plane, column); stride nx
+  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * nx), dim3(ty), 0, s, d, ny, ilog2(ny),
+                     (long long)nx, nx, plane, 1LL, sign);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double kabs(const KParams& p, int ix, int iy) {
+  const int mx = ix < p.nx / 2 ? ix : ix - p.nx;
+  const int my = iy < p.ny / 2 ? iy : iy - p.ny;
+  const double kx = TWO_PI * mx / p.Lx, ky = TWO_PI * my / p.Ly;
+  return sqrt(kx * kx + ky * ky);
+}
+
+// complex planes: 0 = Ax + i Ay (bottom), 1 = Az (bottom), 2 = Ax + i Ay (top), 3 = Az (top)
+__global__ void k_pack_boundary_planes(const KParams p, const double* __restrict__ f,
+                                       double2* __restrict__ S) {
+  const long long sp = p.splane;
+  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < sp;
+       col += (long long)gridDim.x * blockDim.x) {
+    const long long ob = NG * sp + col, ot = (NG + p.nz - 1) * sp + col;
+    S[col] = make_double2(f[AX * p.sfield + ob], f[AY * p.sfield + ob]);
+    S[sp + col] = make_double2(f[AZ * p.sfield + ob], 0.0);
+    S[2 * sp + col] = make_double2(f[AX * p.sfield + ot], f[AY * p.sfield + ot]);
+    S[3 * sp + col] = make_double2(f[AZ * p.sfield + ot], 0.0);
+  }
+}
+
+// T[q*3 + j-1] = S[q] * exp(-|k| d_qj) / (nx ny), d = -f_bot j dz below
+// (contrast grows with depth, Sect. 2.4) and d = j dz above (eq. 17)
+__global__ void k_pf_filter(const KParams p, const double2* __restrict__ S,
+                            double2* __restrict__ T) {
+  const long long sp = p.splane;
+  const double inv_n = 1.0 / double(sp);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < 4 * sp;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int q = int(i / sp);
+    const long long col = i - q * sp;
+    const int iy = int(col / p.nx), ix = int(col - (long long)iy * p.nx);
+    const double k = kabs(p, ix, iy);
+    const double2 v = S[i];
+    const double per = q < 2 ? -p.f_bot * p.dz : p.dz;
+#pragma unroll
+    for (int j = 1; j <= NG; ++j) {
+      const double fac = exp(-k * (j * per)) * inv_n;
+      T[(q * NG + j - 1) * sp + col] = make_double2(v.x * fac, v.y * fac);
+    }
+  }
+}
+
+__global__ void k_unpack_boundary_planes(const KParams p, const double2* __restrict__ T,
+                                         double* __restrict__ f) {
+  const long long sp = p.splane;
+  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < sp;
+       col += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int j = 1; j <= NG; ++j) {
+      const long long ob = (NG - j) * sp + col, ot = (NG + p.nz - 1 + j) * sp + col;
+      const double2 bxy = T[(0 * NG + j - 1) * sp + col];
+      const double2 bz = T[(1 * NG + j - 1) * sp + col];
+      const double2 txy = T[(2 * NG + j - 1) * sp + col];
+      const double2 tz = T[(3 * NG + j - 1) * sp + col];
+      f[AX * p.sfield + ob] = bxy.x;
+      f[AY * p.sfield + ob] = bxy.y;
+      f[AZ * p.sfield + ob] = bz.x;
+      f[AX * p.sfield + ot] = txy.x;
+      f[AY * p.sfield + ot] = txy.y;
+      f[AZ * p.sfield + ot] = tz.x;
+    }
+  }
+}
+
+// A_h* from B_z (eq. 7): A^_x + i A^_y = (k_x + i k_y) B^_z / k^2, zero mean
+// and Nyquist rows/columns, normalised for the inverse transform
+__global__ void k_pack_real(const KParams p, const double* __restrict__ a,
+                            double2* __restrict__ S) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p.splane;
+       i += (long long)gridDim.x * blockDim.x)
+    S[i] = make_double2(a[i], 0.0);
+}
+
+__global__ void k_ah_spectrum(const KParams p, double2* __restrict__ S) {
+  const double inv_n = 1.0 / double(p.splane);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p.splane;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int iy = int(i / p.nx), ix = int(i - (long long)iy * p.nx);
+    const int mx = ix < p.nx / 2 ? ix : ix - p.nx;
+    const int my = iy < p.ny / 2 ? iy : iy - p.ny;
+    if ((mx == 0 && my == 0) || ix == p.nx / 2 || iy == p.ny / 2) {
+      S[i] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double kx = TWO_PI * mx / p.Lx, ky = TWO_PI * my / p.Ly;
+    const double ik2 = inv_n / (kx * kx + ky * ky);
+    const double2 b = S[i];
+    // (kx + i ky) * b
+    S[i] = make_double2((kx * b.x - ky * b.y) * ik2, (kx * b.y + ky * b.x) * ik2);
+  }
+}
+
+__global__ void k_unpack_ah(const KParams p, const double2* __restrict__ S,
+                            double* __restrict__ ah) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p.splane;
+       i += (long long)gridDim.x * blockDim.x) {
+    ah[i] = S[i].x;
+    ah[p.splane + i] = S[i].y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions: CFL maxima, finiteness, net flux
+// ---------------------------------------------------------------------------
+
+// atomic max of non-negative doubles through their bit patterns (monotone)
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double d1col(const double* a, long long s) {
+  return 45.0 * (a[s] - a[-s]) - 9.0 * (a[2 * s] - a[-2 * s]) + (a[3 * s] - a[-3 * s]);
+}
+
+__device__ __forceinline__ long long wrapx(const KParams& p, long long col, int dx) {
+  const int y = int(col / p.nx);
+  int x = int(col - (long long)y * p.nx) + dx;
+  x += x < 0 ? p.nx : 0;
+  x -= x >= p.nx ? p.nx : 0;
+  return (long long)y * p.nx + x;
+}
+__device__ __forceinline__ long long wrapy(const KParams& p, long long col, int dy) {
+  int y = int(col / p.nx);
+  const int x = int(col - (long long)y * p.nx);
+  y += dy;
+  y += y < 0 ? p.ny : 0;
+  y -= y >= p.ny ? p.ny : 0;
+  return (long long)y * p.nx + x;
+}
+
+// first derivative along x or y of field fi at plane-array index kz, column col
+__device__ double d1xy(const KParams& p, const double* f, int fi, int kz, long long col,
+                       int axis) {
+  const double* a = f + fi * p.sfield + (long long)kz * p.splane;
+  double acc = 0.0;
+  const double cf[3] = {45.0, -9.0, 1.0};
+#pragma unroll
+  for (int m = 1; m <= 3; ++m) {
+    const long long cp = axis == 0 ? wrapx(p, col, m) : wrapy(p, col, m);
+    const long long cm = axis == 0 ? wrapx(p, col, -m) : wrapy(p, col, -m);
+    acc += cf[m - 1] * (a[cp] - a[cm]);
+  }
+  return acc * (axis == 0 ? p.i60dx : p.i60dy);
+}
+
+__global__ void k_cfl(const KParams p, const double* __restrict__ f,
+                      unsigned long long* __restrict__ out3) {
+  __shared__ double red[3][256];
+  double ms = 0.0, md = 0.0, mr = 0.0;
+  const long long n = (long long)p.nz * p.splane;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int k = int(i / p.splane);
+    const long long col = i - (long long)k * p.splane;
+    const int kz = k + NG;
+    const long long o = (long long)kz * p.splane + col;
+    const double dAz_dy = d1xy(p, f, AZ, kz, col, 1), dAz_dx = d1xy(p, f, AZ, kz, col, 0);
+    const double dAy_dx = d1xy(p, f, AY, kz, col, 0), dAx_dy = d1xy(p, f, AX, kz, col, 1);
+    const double dAy_dz = d1col(f + AY * p.sfield + o, p.splane) * p.i60dz;
+    const double dAx_dz = d1col(f + AX * p.sfield + o, p.splane) * p.i60dz;
+    const double Bx = dAz_dy - dAy_dz + p.Bext[0];
+    const double By = dAx_dz - dAz_dx + p.Bext[1];
+    const double Bz = dAy_dx - dAx_dy + p.Bext[2];
+    const double ux = f[UX * p.sfield + o], uy = f[UY * p.sfield + o], uz = f[UZ * p.sfield + o];
+    const double lr = f[LR * p.sfield + o], lT = f[LT * p.sfield + o];
+    const double rho = exp(lr), T = exp(lT);
+    const double B2 = Bx * Bx + By * By + Bz * Bz;
+    const double cf = sqrt(p.gamma * p.R * T + B2 / (p.mu0 * rho));
+    const double spd = sqrt(ux * ux + uy * uy + uz * uz) + cf;
+    double w = 0.0;
+    if (p.solar) {
+      const double z = p.z0 + k * p.dz;
+      double s = (z - p.z_s) / (p.z_t - p.z_s);
+      s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+      w = s * s * (3.0 - 2.0 * s);
+    }
+    double D = p.nu;
+    D = fmax(D, p.eta + p.eta_s * w);
+    D = fmax(D, p.D_rho + p.chi_rho * w);
+    D = fmax(D, p.chi_s * w);
+    D = fmax(D, p.kappa0 * exp(2.5 * lT) / (rho * p.cv));
+    double rate = 0.0;
+    if (p.n_rad > 0 && lT > p.lnT_rad_lo) {
+      int seg = 0;
+      for (int j = 1; j < p.n_rad - 1; ++j) seg = (lT >= p.rad_lnT[j]) ? j : seg;
+      double lnL;
+      if (lT < p.rad_lnT[0])
+        lnL = p.rad_lnL[0];
+      else if (lT >= p.rad_lnT[p.n_rad - 1])
+        lnL = p.rad_lnL[p.n_rad - 1];
+      else
+        lnL = p.rad_lnL[seg] + p.rad_slope[seg] * (lT - p.rad_lnT[seg]);
+      double wc = 1.0;
+      if (lT < p.lnT_rad_hi) {
+        const double s = (lT - p.lnT_rad_lo) * p.inv_dlnT_rad;
+        wc = s * s * (3.0 - 2.0 * s);
+      }
+      rate = exp(lr + lnL - lT) * wc / p.cv;   // Q_rad / (rho c_v T)
+    }
+    // NaN propagates: fmax would drop it, so test explicitly
+    ms = (spd > ms || spd != spd) ? spd : ms;
+    md = (D > md || D != D) ? D : md;
+    mr = (rate > mr || rate != rate) ? rate : mr;
+  }
+  red[0][threadIdx.x] = ms;
+  red[1][threadIdx.x] = md;
+  red[2][threadIdx.x] = mr;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double a = red[q][threadIdx.x], b = red[q][threadIdx.x + s];
+        red[q][threadIdx.x] = (b > a || b != b) ? b : a;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) atomic_max_pos(&out3[threadIdx.x], red[threadIdx.x][0]);
+}
+
+__global__ void k_zero_u64(unsigned long long* a, int n) {
+  if ((int)threadIdx.x < n) a[threadIdx.x] = 0ULL;
+}
+
+__global__ void k_bz_plane(const KParams p, const double* __restrict__ f, int k0, double a,
+                           double* __restrict__ dst) {
+  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < p.splane;
+       col += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int q = 0; q < 2; ++q) {
+      const double wq = q == 0 ? 1.0 - a : a;
+      if (wq == 0.0) continue;
+      const int kz = k0 + q + NG;
+      acc += wq * (d1xy(p, f, AY, kz, col, 0) - d1xy(p, f, AX, kz, col, 1));
+    }
+    dst[col] = acc + p.Bext[2];
+  }
+}
+
+__global__ void k_finite(const KParams p, const double* __restrict__ f, int* flag) {
+  const long long n = (long long)NF * p.nz * p.splane;
+  const long long per = (long long)p.nz * p.splane;
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int fi = int(i / per);
+    const long long r = i - fi * per;
+    const double v = f[fi * p.sfield + NG * p.splane + r];
+    bad |= !isfinite(v);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_sum_abs(const KParams p, const double* __restrict__ a, double* out2) {
+  __shared__ double s1[256], s2[256];
+  double x1 = 0.0, x2 = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p.splane;
+       i += (long long)gridDim.x * blockDim.x) {
+    x1 += a[i];
+    x2 += fabs(a[i]);
+  }
+  s1[threadIdx.x] = x1;
+  s2[threadIdx.x] = x2;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+      s2[threadIdx.x] += s2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&out2[0], s1[0]);
+    atomicAdd(&out2[1], s2[0]);
+  }
+}
+
+int grid_for(long long n) {
+  long long b = (n + 255) / 256;
+  return int(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+}  // namespace
+
+hipError_t launch_fill_periodic_z(const KParams& p, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_periodic_z, dim3(grid_for((long long)NF * 2 * NG * p.splane)),
+                     dim3(256), 0, s, p, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_solar_columns(const KParams& p, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_solar_columns, dim3(grid_for(p.splane)), dim3(256), 0, s, p, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch,
+                                   hipStream_t s) {
+  double2* S = scratch;                 // 4 planes
+  double2* T = scratch + 4 * p.splane;  // 12 planes
+  hipLaunchKernelGGL(k_pack_boundary_planes, dim3(grid_for(p.splane)), dim3(256), 0, s, p, f, S);
+  hipError_t e = fft2d(p, S, 4, -1.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pf_filter, dim3(grid_for(4 * p.splane)), dim3(256), 0, s, p, S, T);
+  e = fft2d(p, T, 4 * NG, +1.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_boundary_planes, dim3(grid_for(p.splane)), dim3(256), 0, s, p, T,
+                     f);
+  return hipGetLastError();
+}
+
+hipError_t launch_ah_from_bz(const KParams& p, const double* bz, double* ah, double2* scratch,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_real, dim3(grid_for(p.splane)), dim3(256), 0, s, p, bz, scratch);
+  hipError_t e = fft2d(p, scratch, 1, -1.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ah_spectrum, dim3(grid_for(p.splane)), dim3(256), 0, s, p, scratch);
+  e = fft2d(p, scratch, 1, +1.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_ah, dim3(grid_for(p.splane)), dim3(256), 0, s, p, scratch, ah);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_max(const KParams& p, const double* f, unsigned long long* out3,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out3, 3);
+  hipLaunchKernelGGL(k_cfl, dim3(grid_for((long long)p.nz * p.splane)), dim3(256), 0, s, p, f,
+                     out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_bz_plane(const KParams& p, const double* f, double zq, double* dst,
+                           hipStream_t s) {
+  const double kf = (zq - p.z0) / p.dz;
+  int k0 = int(floor(kf));
+  double a = kf - k0;
+  if (k0 >= p.nz - 1) {
+    k0 = p.nz - 2;
+    a = 1.0;
+  }
+  hipLaunchKernelGGL(k_bz_plane, dim3(grid_for(p.splane)), dim3(256), 0, s, p, f, k0, a, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const KParams& p, const double* f, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_finite, dim3(grid_for((long long)NF * p.nz * p.splane)), dim3(256), 0, s,
+                     p, f, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_abs(const KParams& p, const double* plane, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_abs, dim3(grid_for(p.splane)), dim3(256), 0, s, p, plane, out2);
+  return hipGetLastError();
+}
+
+}  // namespace cmhd

@@ -1,0 +1,458 @@
+// C ABI of the library (declared in include/cmhd.h): context, validation,
+// workspace binding and the substage sequence of one RK3 step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "cmhd_internal.h"
+
+using namespace cmhd;
+
+struct cmhd_ctx {
+  cmhd_grid grid;
+  cmhd_params par;
+  KParams kp;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* W1 = nullptr;   // stage buffers
+  double* W2 = nullptr;
+  double* dF = nullptr;   // RK register
+  double* uh = nullptr;   // driver u*      [2][ny][nx]
+  double* ah = nullptr;   // A_h* target    [2][ny][nx]
+  double2* fft = nullptr; // Fourier scratch
+  unsigned long long* red = nullptr;  // reduction scratch
+  std::string err;
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+  ~cmhd_ctx() {
+    for (auto& e : ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  }
+};
+
+namespace {
+
+cmhd_status fail(cmhd_ctx* c, cmhd_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+cmhd_status hip_check(cmhd_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return CMHD_OK;
+  return fail(c, CMHD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t state_elems(const cmhd_grid& g) {
+  return size_t(NF) * size_t(g.nz + 2 * NG) * size_t(g.ny) * size_t(g.nx);
+}
+
+size_t ws_layout(const cmhd_ctx* c, size_t off[8]) {
+  const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
+  const size_t sb = align256(state_elems(c->grid) * sizeof(double));
+  size_t o = 0;
+  off[0] = o; o += sb;                                           // W1
+  off[1] = o; o += sb;                                           // W2
+  off[2] = o; o += sb;                                           // dF
+  off[3] = o; o += align256(2 * plane * sizeof(double));         // uh
+  off[4] = o; o += align256(2 * plane * sizeof(double));         // ah
+  off[5] = o; o += align256(FFT_PLANES * plane * sizeof(double2));  // fft
+  off[6] = o; o += 256;                                          // reductions
+  return o;
+}
+
+void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
+  const cmhd_grid& g = c->grid;
+  const cmhd_params& q = c->par;
+  KParams& p = c->kp;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = g.nx;
+  p.ny = g.ny;
+  p.nz = g.nz;
+  p.solar = g.zbc == CMHD_ZBC_SOLAR;
+  p.splane = (long long)g.nx * g.ny;
+  p.sfield = (long long)(g.nz + 2 * NG) * p.splane;
+  p.dx = g.Lx / g.nx;
+  p.dy = g.Ly / g.ny;
+  p.dz = p.solar ? (g.z1 - g.z0) / (g.nz - 1) : (g.z1 - g.z0) / g.nz;
+  p.z0 = g.z0;
+  p.Lx = g.Lx;
+  p.Ly = g.Ly;
+  p.i60dx = 1.0 / (60.0 * p.dx);
+  p.i60dy = 1.0 / (60.0 * p.dy);
+  p.i60dz = 1.0 / (60.0 * p.dz);
+  p.i180dx2 = 1.0 / (180.0 * p.dx * p.dx);
+  p.i180dy2 = 1.0 / (180.0 * p.dy * p.dy);
+  p.i180dz2 = 1.0 / (180.0 * p.dz * p.dz);
+  p.gamma = q.gamma;
+  p.R = q.R;
+  p.mu0 = q.mu0;
+  p.inv_mu0 = 1.0 / q.mu0;
+  p.eta = q.eta;
+  p.nu = q.nu;
+  p.D_rho = q.D_rho;
+  p.kappa0 = q.kappa0;
+  p.g_z = q.g_z;
+  p.cv = q.R / (q.gamma - 1.0);
+  p.gm1 = q.gamma - 1.0;
+  for (int i = 0; i < 3; ++i) p.Bext[i] = q.Bext[i];
+  p.B_floor2 = q.B_floor * q.B_floor;
+  if (p.solar) {
+    p.eta_s = q.eta_s;
+    p.chi_s = q.chi_s;
+    p.chi_rho = q.chi_rho;
+    p.z_s = q.z_s;
+    p.z_t = q.z_t;
+    p.tau_u = q.tau_u;
+    p.tau_A = q.tau_A;
+  } else {
+    p.z_s = 0.0;
+    p.z_t = 1.0;
+  }
+  p.f_bot = q.f_bot;
+  p.n_rad = q.n_rad;
+  for (int i = 0; i < q.n_rad; ++i) {
+    p.rad_lnT[i] = q.rad_lnT[i];
+    p.rad_lnL[i] = q.rad_lnL[i];
+  }
+  for (int i = 0; i + 1 < q.n_rad; ++i)
+    p.rad_slope[i] = (q.rad_lnL[i + 1] - q.rad_lnL[i]) / (q.rad_lnT[i + 1] - q.rad_lnT[i]);
+  p.lnT_rad_lo = std::log(q.T_rad_lo);
+  p.lnT_rad_hi = std::log(q.T_rad_hi);
+  p.inv_dlnT_rad = 1.0 / (p.lnT_rad_hi - p.lnT_rad_lo);
+  for (int i = 0; i < 4; ++i) p.lnrho0_bot[i] = lnrho0_z ? lnrho0_z[i] : 0.0;
+  p.c_adv = q.c_adv;
+  p.c_diff = q.c_diff;
+  p.c_nudge = q.c_nudge;
+}
+
+double ramp(const cmhd_ctx* c, double t) {
+  if (c->par.t_ramp <= 0.0) return 1.0;
+  const double r = t / c->par.t_ramp;
+  return r < 1.0 ? r : 1.0;
+}
+
+cmhd_status need_ws(cmhd_ctx* c) {
+  if (!c->ws) return fail(c, CMHD_ESTATE, "no workspace bound (cmhd_bind_workspace)");
+  return CMHD_OK;
+}
+
+cmhd_status do_fill(cmhd_ctx* c, double* state) {
+  hipError_t e;
+  if (c->kp.solar) {
+    e = launch_fill_solar_columns(c->kp, state, c->stream);
+    if (e == hipSuccess) e = launch_potential_ghosts(c->kp, state, c->fft, c->stream);
+  } else {
+    e = launch_fill_periodic_z(c->kp, state, c->stream);
+  }
+  return hip_check(c, e, "fill_ghosts launch");
+}
+
+cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
+  cmhd_status st = do_fill(c, state);
+  if (st != CMHD_OK) return st;
+  hipError_t e = launch_cfl_max(c->kp, state, c->red, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "cfl launch");
+  unsigned long long h[3];
+  e = hipMemcpyAsync(h, c->red, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "cfl copy");
+  double m[3];
+  std::memcpy(m, h, sizeof(m));
+  const KParams& p = c->kp;
+  double delta = std::fmin(p.dx, std::fmin(p.dy, p.dz));
+  double dt = p.c_adv * delta / m[0];
+  if (m[1] > 0.0) dt = std::fmin(dt, p.c_diff * delta * delta / m[1]);
+  if (m[2] > 0.0) dt = std::fmin(dt, p.c_adv / m[2]);
+  const double tau = std::fmax(p.tau_u, p.tau_A);
+  if (p.solar && tau > 0.0) dt = std::fmin(dt, p.c_nudge / tau);
+  if (!(dt > 0.0) || !std::isfinite(dt) || std::isnan(m[0]) || std::isnan(m[1]) ||
+      std::isnan(m[2]))
+    return fail(c, CMHD_ENONFINITE, "time step is not finite (state holds NaN/Inf?)");
+  *dt_out = dt;
+  return CMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
+                           const double* lnrho0_z, void* stream, cmhd_ctx** out) {
+  if (!out) return CMHD_EINVAL;
+  *out = nullptr;
+  if (!grid || !params) return CMHD_EINVAL;
+  const cmhd_grid& g = *grid;
+  const cmhd_params& q = *params;
+  const bool solar = g.zbc == CMHD_ZBC_SOLAR;
+  std::string why;
+  if (!pow2(g.nx) || !pow2(g.ny) || g.nx < 16 || g.ny < 16 || g.nx > 1024 || g.ny > 1024)
+    why = "nx, ny must be powers of two in [16, 1024]";
+  else if (g.nz < 8)
+    why = "nz must be >= 8";
+  else if (g.zbc != CMHD_ZBC_PERIODIC && g.zbc != CMHD_ZBC_SOLAR)
+    why = "zbc must be CMHD_ZBC_PERIODIC or CMHD_ZBC_SOLAR";
+  else if (g.prec != CMHD_FP64 && g.prec != CMHD_FP32_SPLIT)
+    why = "prec must be CMHD_FP64 or CMHD_FP32_SPLIT";
+  else if (!(g.Lx > 0) || !(g.Ly > 0) || !(g.z1 > g.z0))
+    why = "domain lengths must be positive";
+  else if (!(q.gamma > 1.0) || !(q.R > 0) || !(q.mu0 > 0))
+    why = "gamma > 1, R > 0 and mu0 > 0 are required";
+  else if (q.eta < 0 || q.nu < 0 || q.D_rho < 0 || q.kappa0 < 0)
+    why = "diffusivities must be non-negative";
+  else if (q.n_rad < 0 || q.n_rad == 1 || q.n_rad > CMHD_MAX_RAD)
+    why = "n_rad must be 0 or in [2, 16]";
+  else if (q.n_rad > 0 && !(q.T_rad_hi > q.T_rad_lo && q.T_rad_lo > 0))
+    why = "0 < T_rad_lo < T_rad_hi is required";
+  else if (solar && !(q.z_t > q.z_s))
+    why = "z_t > z_s is required";
+  else if (solar && !lnrho0_z)
+    why = "solar mode needs the ln rho0(z) profile";
+  for (int i = 0; why.empty() && i + 1 < q.n_rad; ++i)
+    if (!(q.rad_lnT[i + 1] > q.rad_lnT[i])) why = "rad_lnT must increase";
+  if (!why.empty()) {
+    std::fprintf(stderr, "cmhd_init_grid: %s\n", why.c_str());
+    return CMHD_EINVAL;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    std::fprintf(stderr, "cmhd_init_grid: no HIP device\n");
+    return CMHD_EDEVICE;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    std::fprintf(stderr, "cmhd_init_grid: device is %s, the library is built for gfx950\n",
+                 prop.gcnArchName);
+    return CMHD_EDEVICE;
+  }
+  cmhd_ctx* c = new cmhd_ctx();
+  c->grid = g;
+  c->par = q;
+  c->stream = (hipStream_t)stream;
+  fill_kparams(c, lnrho0_z);
+  *out = c;
+  return CMHD_OK;
+}
+
+size_t cmhd_state_elems(const cmhd_ctx* c) { return c ? state_elems(c->grid) : 0; }
+
+size_t cmhd_workspace_bytes(const cmhd_ctx* c) {
+  if (!c) return 0;
+  size_t off[8];
+  return ws_layout(c, off);
+}
+
+cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return CMHD_EINVAL;
+  size_t off[8];
+  const size_t need = ws_layout(c, off);
+  if (!dev_ptr) return fail(c, CMHD_EINVAL, "workspace pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0)
+    return fail(c, CMHD_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need)
+    return fail(c, CMHD_EWORKSPACE,
+                "workspace too small: " + std::to_string(bytes) + " < " + std::to_string(need));
+  c->ws = static_cast<char*>(dev_ptr);
+  c->ws_bytes = bytes;
+  c->W1 = reinterpret_cast<double*>(c->ws + off[0]);
+  c->W2 = reinterpret_cast<double*>(c->ws + off[1]);
+  c->dF = reinterpret_cast<double*>(c->ws + off[2]);
+  c->uh = reinterpret_cast<double*>(c->ws + off[3]);
+  c->ah = reinterpret_cast<double*>(c->ws + off[4]);
+  c->fft = reinterpret_cast<double2*>(c->ws + off[5]);
+  c->red = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
+  // driver targets start at zero; the stage buffers are fully written before use
+  const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
+  hipError_t e = hipMemsetAsync(c->uh, 0, 2 * plane * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ah, 0, 2 * plane * sizeof(double), c->stream);
+  return hip_check(c, e, "workspace clear");
+}
+
+cmhd_status cmhd_set_stream(cmhd_ctx* c, void* stream) {
+  if (!c) return CMHD_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_set_driver(cmhd_ctx* c, const double* uh, const double* bz, const double* ah) {
+  if (!c) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  if (!uh) return fail(c, CMHD_EINVAL, "uh is NULL");
+  if (bz && ah) return fail(c, CMHD_EINVAL, "give bz or ah, not both");
+  const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
+  hipError_t e = hipMemcpyAsync(c->uh, uh, 2 * plane * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "driver copy");
+  if (ah) {
+    e = hipMemcpyAsync(c->ah, ah, 2 * plane * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "driver copy");
+  }
+  if (bz) {
+    // balanced flux (Sect. 2.1): |sum B_z| <= 1e-12 sum |B_z|
+    double* red2 = reinterpret_cast<double*>(c->red) + 4;
+    e = hipMemsetAsync(red2, 0, 2 * sizeof(double), c->stream);
+    if (e == hipSuccess) e = launch_sum_abs(c->kp, bz, red2, c->stream);
+    double h[2] = {0, 0};
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h, red2, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "net flux");
+    if (std::fabs(h[0]) > 1e-12 * h[1])
+      return fail(c, CMHD_EINVAL, "B_z has a net flux (sum " + std::to_string(h[0]) + ")");
+    e = launch_ah_from_bz(c->kp, bz, c->ah, c->fft, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "A_h* from B_z");
+  }
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_fill_ghosts(cmhd_ctx* c, double* state, double t) {
+  (void)t;
+  if (!c || !state) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  return do_fill(c, state);
+}
+
+cmhd_status cmhd_cfl_dt(cmhd_ctx* c, double* state, double* dt_out) {
+  if (!c || !state || !dt_out) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  return do_cfl(c, state, dt_out);
+}
+
+cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, double* dt_used) {
+  if (!c || !state || !t) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  if (!(dt > 0.0)) {
+    st = do_cfl(c, state, &dt);
+    if (st != CMHD_OK) return st;
+  }
+  double* src[3] = {state, c->W1, c->W2};
+  double* dst[3] = {c->W1, c->W2, state};
+  for (int s = 0; s < 3; ++s) {
+    st = do_fill(c, src[s]);
+    if (st != CMHD_OK) return st;
+    StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, *t + RK_C[s] * dt)};
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->profiling) {
+      if (!c->ev_free.empty()) {
+        ev = c->ev_free.back();
+        c->ev_free.pop_back();
+      } else if (hipEventCreate(&ev.first) != hipSuccess ||
+                 hipEventCreate(&ev.second) != hipSuccess) {
+        return fail(c, CMHD_EDEVICE, "event creation failed");
+      }
+      (void)hipEventRecord(ev.first, c->stream);
+    }
+    hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, s, src[s], dst[s], c->dF, c->uh, c->ah, a,
+                                 c->stream);
+    if (c->profiling) {
+      (void)hipEventRecord(ev.second, c->stream);
+      c->ev_pending.push_back(ev);
+    }
+    if (e == hipSuccess && c->kp.solar)
+      e = launch_ghost_rows(c->kp, src[s], dst[s], c->dF, c->uh, a, s > 0, s < 2, c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "rk3 substage launch");
+  }
+  *t += dt;
+  if (dt_used) *dt_used = dt;
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_eval_rhs(cmhd_ctx* c, double* state, double t, double* rhs) {
+  if (!c || !state || !rhs) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  st = do_fill(c, state);
+  if (st != CMHD_OK) return st;
+  // one substage with alpha = 0, beta = 0, dt = 1: dF = RHS, f_next = f (into W1)
+  StageArgs a{0.0, 0.0, 1.0, ramp(c, t)};
+  hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, 0, state, c->W1, rhs, c->uh, c->ah, a,
+                               c->stream);
+  if (e == hipSuccess && c->kp.solar)
+    e = launch_ghost_rows(c->kp, state, c->W1, rhs, c->uh, a, 0, 1, c->stream);
+  return hip_check(c, e, "eval_rhs launch");
+}
+
+cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, double* dst,
+                            int dst_on_host, int with_ghosts) {
+  if (!c || !state || !dst) return CMHD_EINVAL;
+  if (mask == 0 || mask > 0xFFu) return fail(c, CMHD_EINVAL, "mask selects no valid field");
+  const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
+  const size_t nzc = with_ghosts ? size_t(c->grid.nz + 2 * NG) : size_t(c->grid.nz);
+  const size_t off = with_ghosts ? 0 : NG * plane;
+  const size_t per = nzc * plane;
+  const size_t sfield = size_t(c->grid.nz + 2 * NG) * plane;
+  const hipMemcpyKind kind = dst_on_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  size_t o = 0;
+  for (int f = 0; f < NF; ++f) {
+    if (!(mask & (1u << f))) continue;
+    hipError_t e = hipMemcpyAsync(dst + o, state + f * sfield + off, per * sizeof(double), kind,
+                                  c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "get_fields copy");
+    o += per;
+  }
+  if (dst_on_host) return hip_check(c, hipStreamSynchronize(c->stream), "get_fields sync");
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_bz_plane(cmhd_ctx* c, const double* state, double z, double* dst) {
+  if (!c || !state || !dst) return CMHD_EINVAL;
+  const KParams& p = c->kp;
+  if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
+    return fail(c, CMHD_EINVAL, "z outside the interior");
+  return hip_check(c, launch_bz_plane(p, state, z, dst, c->stream), "bz_plane launch");
+}
+
+cmhd_status cmhd_check_finite(cmhd_ctx* c, const double* state) {
+  if (!c || !state) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  int* flag = reinterpret_cast<int*>(c->red + 6);
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
+  if (e == hipSuccess) e = launch_finite_check(c->kp, state, flag, c->stream);
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "finite check");
+  return h ? fail(c, CMHD_ENONFINITE, "state holds a non-finite value") : CMHD_OK;
+}
+
+cmhd_status cmhd_profile_enable(cmhd_ctx* c, int enable) {
+  if (!c) return CMHD_EINVAL;
+  c->profiling = enable != 0;
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_profile_read(cmhd_ctx* c, double* ms, int* launches) {
+  if (!c || !ms || !launches) return CMHD_EINVAL;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "profile sync");
+  double sum = 0.0;
+  for (auto& ev : c->ev_pending) {
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, ev.first, ev.second);
+    if (e != hipSuccess) return hip_check(c, e, "event elapsed");
+    sum += t;
+    c->ev_free.push_back(ev);
+  }
+  *launches = int(c->ev_pending.size());
+  c->ev_pending.clear();
+  *ms = sum;
+  return CMHD_OK;
+}
+
+const char* cmhd_last_error(const cmhd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void cmhd_destroy(cmhd_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal declarations of the gfx950 MHD library: kernel parameter block,
+// field indices, tile geometry and the launch helpers shared by the
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cmhd.h"
+
+namespace cmhd {
+
+constexpr int NG = 3;   // ghost planes per side (three ghost layers, Sect. 2.3-4.2)
+constexpr int NF = 8;   // Ax Ay Az ux uy uz lnrho lnT
+enum Field { AX = 0, AY, AZ, UX, UY, UZ, LR, LT };
+
+// Tile of the fused stencil kernel: 16 x 16 columns, one thread per column,
+// marching in z; the x/y halo of 3 points makes a 22 x 22 plane in LDS.
+constexpr int TX = 16, TY = 16, NT = TX * TY;
+constexpr int HX = TX + 2 * NG, HY = TY + 2 * NG, HP = HX * HY;
+constexpr int NHALO = HP - NT;   // 228 halo points per plane
+
+// Parameter block handed to every kernel by value.
+struct KParams {
+  int nx, ny, nz, solar;
+  long long splane;   // nx*ny: z stride
+  long long sfield;   // (nz+6)*nx*ny: field stride
+  double dx, dy, dz, z0;
+  double i60dx, i60dy, i60dz;      // 1/(60 h)
+  double i180dx2, i180dy2, i180dz2;  // 1/(180 h^2)
+  double gamma, R, mu0, inv_mu0, eta, nu, D_rho, kappa0, g_z, cv, gm1;
+  double Bext[3];
+  double B_floor2;
+  double eta_s, chi_s, chi_rho, z_s, z_t;
+  double tau_u, tau_A, f_bot;
+  int n_rad;
+  double rad_lnT[CMHD_MAX_RAD], rad_lnL[CMHD_MAX_RAD], rad_slope[CMHD_MAX_RAD];
+  double lnT_rad_lo, lnT_rad_hi, inv_dlnT_rad;
+  double lnrho0_bot[4];   // ln rho0 at k = -3, -2, -1, 0
+  double Lx, Ly;
+  double c_adv, c_diff, c_nudge;
+};
+
+// Per-substage arguments of the Runge-Kutta update.
+struct StageArgs {
+  double alpha, beta, dt, ramp;
+};
+
+// Williamson (1980) 2N-storage RK3.
+constexpr double RK_ALPHA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+constexpr double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+constexpr double RK_C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
+
+// Launchers (each returns the hipError_t of its launch).
+hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, double* fo,
+                         double* dF, const double* uh, const double* ah, StageArgs st,
+                         hipStream_t s);
+hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,
+                             const double* uh, StageArgs st, int read_dF, int write_dF,
+                             hipStream_t s);
+hipError_t launch_fill_periodic_z(const KParams& p, double* f, hipStream_t s);
+hipError_t launch_fill_solar_columns(const KParams& p, double* f, hipStream_t s);
+hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch,
+                                   hipStream_t s);
+hipError_t launch_ah_from_bz(const KParams& p, const double* bz, double* ah, double2* scratch,
+                             hipStream_t s);
+hipError_t launch_cfl_max(const KParams& p, const double* f, unsigned long long* out3,
+                          hipStream_t s);
+hipError_t launch_bz_plane(const KParams& p, const double* f, double zq, double* dst,
+                           hipStream_t s);
+hipError_t launch_finite_check(const KParams& p, const double* f, int* flag, hipStream_t s);
+hipError_t launch_sum_abs(const KParams& p, const double* plane, double* out2, hipStream_t s);
+
+// Scratch of the Fourier boundary: complex planes needed by
+// launch_potential_ghosts (4 forward + 12 filtered).
+constexpr int FFT_PLANES = 16;
+
+__host__ __device__ inline int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+}  // namespace cmhd
