@@ -35,10 +35,37 @@ __device__ __forceinline__ double dxyu(const double* a, int c) {
          (d1u(a, c + 3 * HX, 1) - d1u(a, c - 3 * HX, 1));
 }
 
-// keeps the scheduler from hoisting the LDS reads of later groups
-#define SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 
-__device__ __forceinline__ int zslot(int f) { return f < LR ? f : 6; }  // Zs index of A, u, lnT
+// Derivatives at the own column, read from the staged plane on demand.
+template <typename Real>
+struct LdsSource {
+  static constexpr int kUnroll = 1;   // rolled component loops
+  const double (*P)[HP];
+  const Real (*Zs)[HP];
+  const double (*D2z)[NT];
+  int c, t;
+  double i60dx, i60dy, i180dx2, i180dy2;
+  __device__ __forceinline__ Real v(int f) const { return Real(P[f][c]); }
+  __device__ __forceinline__ double v64(int f) const { return P[f][c]; }
+  __device__ __forceinline__ Real d(int f, int dir) const {
+    if (dir == 0) return Real(d1u(P[f], c, 1) * i60dx);
+    if (dir == 1) return Real(d1u(P[f], c, HX) * i60dy);
+    return Zs[f][c];
+  }
+  __device__ __forceinline__ Real h(int f, int slot) const {
+    switch (slot) {
+      case 0: return Real(d2u(P[f], c, 1) * i180dx2);
+      case 1: return Real(d2u(P[f], c, HX) * i180dy2);
+      case 2: return Real(D2z[f][t]);
+      case 3: return Real(dxyu(P[f], c) * (i60dx * i60dy));
+      case 4: return d1u(Zs[f], c, 1) * Real(i60dx);
+      default: return d1u(Zs[f], c, HX) * Real(i60dy);
+    }
+  }
+  __device__ __forceinline__ Real lapr() const {
+    return Real(d2u(P[LR], c, 1) * i180dx2 + d2u(P[LR], c, HX) * i180dy2 + D2z[LR][t]);
+  }
+};
 
 __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double& dw) {
   w = 0.0;
@@ -60,7 +87,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                                const double* __restrict__ ah, const KParams p,
                                                const StageArgs st, int kchunk) {
   __shared__ double P[NF][HP];
-  __shared__ Real Zs[7][HP];
+  __shared__ Real Zs[NF][HP];     // d/dz (the ln rho slot only at the tile's own columns)
+  __shared__ double D2z[NF][NT];  // d2/dz2 at the tile's own columns
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -100,106 +128,37 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     const long long zo = (long long)(k + NG) * sp;
 
     // ---- stage plane k: own column (values, d/dz, d2/dz2) and one halo column.
-    // Addresses: a wave-uniform base per field and plane plus 32-bit
-    // per-thread offsets, so that no per-(field, plane) 64-bit pointer is
-    // kept alive across the z loop.
-    double d2z[NF];
-    double d1z_lr = 0.0;
-#pragma unroll
+    // Addresses: a wave-uniform base at plane k-3 per field plus non-negative
+    // 32-bit per-thread offsets (no 64-bit pointer per field and plane).
+    const long long zb = (long long)k * sp;   // plane k-3 in array planes
+    // one field at a time (rolled loop: keeps the loads in flight, and so the
+    // registers, bounded)
+#pragma unroll 1
     for (int fi = 0; fi < NF; ++fi) {
-      const double* __restrict__ fb = f + (fi * sf + zo);
-      const double m3 = fb[oc - 3 * sp32], m2 = fb[oc - 2 * sp32], m1 = fb[oc - sp32];
-      const double c0 = fb[oc];
-      const double p1 = fb[oc + sp32], p2 = fb[oc + 2 * sp32], p3 = fb[oc + 3 * sp32];
+      const double* __restrict__ fb = f + (fi * sf + zb);
+      const double m3 = fb[oc], m2 = fb[oc + sp32], m1 = fb[oc + 2 * sp32];
+      const double c0 = fb[oc + 3 * sp32];
+      const double p1 = fb[oc + 4 * sp32], p2 = fb[oc + 5 * sp32], p3 = fb[oc + 6 * sp32];
       P[fi][c] = c0;
-      const double d1 = (45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) * p.i60dz;
-      d2z[fi] = (-490.0 * c0 + 270.0 * (p1 + m1) - 27.0 * (p2 + m2) + 2.0 * (p3 + m3)) *
-                p.i180dz2;
-      if (fi == LR)
-        d1z_lr = d1;
-      else
-        Zs[zslot(fi)][c] = Real(d1);
-      SCHED_FENCE();
-    }
-    if (hc >= 0) {
-#pragma unroll
-      for (int fi = 0; fi < NF; ++fi) {
-        const double* __restrict__ fb = f + (fi * sf + zo);
-        P[fi][hc] = fb[oh];
+      Zs[fi][c] = Real((45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) * p.i60dz);
+      D2z[fi][tid] = (-490.0 * c0 + 270.0 * (p1 + m1) - 27.0 * (p2 + m2) + 2.0 * (p3 + m3)) *
+                     p.i180dz2;
+      if (hc >= 0) {
+        P[fi][hc] = fb[oh + 3 * sp32];
         if (fi != LR) {
-          const double d1 = (45.0 * (fb[oh + sp32] - fb[oh - sp32]) -
-                             9.0 * (fb[oh + 2 * sp32] - fb[oh - 2 * sp32]) +
-                             (fb[oh + 3 * sp32] - fb[oh - 3 * sp32])) *
+          const double d1 = (45.0 * (fb[oh + 4 * sp32] - fb[oh + 2 * sp32]) -
+                             9.0 * (fb[oh + 5 * sp32] - fb[oh + sp32]) +
+                             (fb[oh + 6 * sp32] - fb[oh])) *
                             p.i60dz;
-          Zs[zslot(fi)][hc] = Real(d1);
+          Zs[fi][hc] = Real(d1);
         }
-        SCHED_FENCE();
       }
     }
     __syncthreads();
 
-    // ---- derivatives at the own column from LDS, folded field by field
-    PointIn<Real> in;
+    // ---- pointwise right-hand side, derivatives read from LDS on demand
+    LdsSource<Real> src{P, Zs, D2z, c, tid, p.i60dx, p.i60dy, p.i180dx2, p.i180dy2};
     PointCtx<Real> pc;
-    const Real sx = Real(p.i60dx), sy = Real(p.i60dy);
-    const double sxy = p.i60dx * p.i60dy;
-#pragma unroll
-    for (int fi = 0; fi < NF; ++fi) in.v[fi] = Real(P[fi][c]);
-    in.lr64 = P[LR][c];
-    in.lT64 = P[LT][c];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) in.dB[i][j] = Real(0.0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      in.GA[a][0] = Real(d1u(P[AX + a], c, 1) * p.i60dx);
-      in.GA[a][1] = Real(d1u(P[AX + a], c, HX) * p.i60dy);
-      in.GA[a][2] = Zs[AX + a][c];
-      Real h[6];
-      h[0] = Real(d2u(P[AX + a], c, 1) * p.i180dx2);
-      h[1] = Real(d2u(P[AX + a], c, HX) * p.i180dy2);
-      h[2] = Real(d2z[AX + a]);
-      h[3] = Real(dxyu(P[AX + a], c) * sxy);
-      h[4] = d1u(Zs[AX + a], c, 1) * sx;
-      h[5] = d1u(Zs[AX + a], c, HX) * sy;
-      fold_A_hessian<Real>(AX + a, h, in.dB, in.lapA);
-      SCHED_FENCE();
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) in.graddiv[i] = Real(0.0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      in.Gu[a][0] = Real(d1u(P[UX + a], c, 1) * p.i60dx);
-      in.Gu[a][1] = Real(d1u(P[UX + a], c, HX) * p.i60dy);
-      in.Gu[a][2] = Zs[UX + a][c];
-      Real h[6];
-      h[0] = Real(d2u(P[UX + a], c, 1) * p.i180dx2);
-      h[1] = Real(d2u(P[UX + a], c, HX) * p.i180dy2);
-      h[2] = Real(d2z[UX + a]);
-      // mixed slots of grad div u: xy for u_x, u_y; xz for u_x, u_z; yz for u_y, u_z
-      h[3] = a != 2 ? Real(dxyu(P[UX + a], c) * sxy) : Real(0.0);
-      h[4] = a != 1 ? d1u(Zs[UX + a], c, 1) * sx : Real(0.0);
-      h[5] = a != 0 ? d1u(Zs[UX + a], c, HX) * sy : Real(0.0);
-      fold_u_hessian<Real>(a, h, in.lapu, in.graddiv);
-      SCHED_FENCE();
-    }
-    in.Glr[0] = Real(d1u(P[LR], c, 1) * p.i60dx);
-    in.Glr[1] = Real(d1u(P[LR], c, HX) * p.i60dy);
-    in.Glr[2] = Real(d1z_lr);
-    in.lapr = Real(d2u(P[LR], c, 1) * p.i180dx2 + d2u(P[LR], c, HX) * p.i180dy2 + d2z[LR]);
-    SCHED_FENCE();
-    in.GlT[0] = Real(d1u(P[LT], c, 1) * p.i60dx);
-    in.GlT[1] = Real(d1u(P[LT], c, HX) * p.i60dy);
-    in.GlT[2] = Zs[6][c];
-    in.HT[0] = Real(d2u(P[LT], c, 1) * p.i180dx2);
-    in.HT[1] = Real(d2u(P[LT], c, HX) * p.i180dy2);
-    in.HT[2] = Real(d2z[LT]);
-    in.HT[3] = Real(dxyu(P[LT], c) * sxy);
-    in.HT[4] = d1u(Zs[6], c, 1) * sx;
-    in.HT[5] = d1u(Zs[6], c, HX) * sy;
-
-    SCHED_FENCE();
     swamp(p, k, pc.w, pc.dw);
     pc.bottom = SOLAR && k == 0;
     pc.top = SOLAR && k == p.nz - 1;
@@ -214,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     }
 
     Real out[NF];
-    rhs_point<Real>(in, pc, p, out);
+    rhs_eval<Real>(src, pc, p, out);
 
     // ---- 2N-RK3 register update in float64
 #pragma unroll
