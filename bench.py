@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--workload", default="strat512")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -116,6 +118,17 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mib:
+        # a plain copy of known size: FETCH_SIZE/WRITE_SIZE per dispatch of this
+        # kernel give the scale of the HBM counters
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": args.steps}))
+        return
     from paper_1908_08557_amd import workloads as W
 
     log(f"[bench] building workload {args.workload}")
