@@ -186,6 +186,34 @@ cmhd_status cmhd_bz_plane(cmhd_ctx* ctx, const double* state, double z, double* 
  * Returns CMHD_ENONFINITE otherwise. */
 cmhd_status cmhd_check_finite(cmhd_ctx* ctx, const double* state);
 
+/* ---- tangent-linear and adjoint step (differentiation of cmhd_rk3_step) ----
+ * The step is differentiated as the discrete map it is, at fixed t and dt:
+ *   y = Step(x, u*)    (x: the state entries, i.e. the interior of every
+ *                       field and, in solar mode, the ux, uy lower ghost rows;
+ *                       u*: the driver target of eq. (5))
+ * The pointwise right-hand side is differentiated with forward-mode dual
+ * numbers; the stencil, ghost-rule, Fourier-filter and Runge-Kutta transposes
+ * are written out.  Entries of x, dx, ybar that are not state entries are
+ * ignored; those of dy and xbar are returned as zero.  Calls need a bound
+ * adjoint workspace (ESTATE otherwise) and recompute the forward substages
+ * into the step workspace.  x is not modified except for its derived ghosts. */
+size_t cmhd_adjoint_workspace_bytes(const cmhd_ctx* ctx);
+cmhd_status cmhd_bind_adjoint_workspace(cmhd_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* dy = (d Step/d x) dx + (d Step/d u*) duh.  duh: device [2][ny][nx] or NULL
+ * (no driver perturbation).  dx, dy: device, state layout. */
+cmhd_status cmhd_rk3_step_jvp(cmhd_ctx* ctx, double* x, double t, double dt, const double* dx,
+                              const double* duh, double* dy);
+
+/* xbar = (d Step/d x)^T ybar (overwritten); uhbar += (d Step/d u*)^T ybar
+ * (device [2][ny][nx], accumulated; may be NULL). */
+cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* ctx, double* x, double t, double dt, const double* ybar,
+                              double* xbar, double* uhbar);
+
+/* xbar += (d B_z-plane / d x)^T bzbar for the plane of cmhd_bz_plane at height
+ * z (the loss of a magnetogram fit at that height). */
+cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* ctx, double z, const double* bzbar, double* xbar);
+
 /* Kernel timing.  While enabled, cmhd_rk3_step records a pair of HIP events
  * on the context stream around every launch of the fused substage kernel.
  * cmhd_profile_read synchronises the stream, returns the summed duration in

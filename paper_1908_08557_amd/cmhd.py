@@ -75,6 +75,11 @@ def load():
         "cmhd_get_fields": (I, [P, P, U, P, I, I]),
         "cmhd_bz_plane": (I, [P, P, D, P]),
         "cmhd_check_finite": (I, [P, P]),
+        "cmhd_adjoint_workspace_bytes": (S, [P]),
+        "cmhd_bind_adjoint_workspace": (I, [P, P, S]),
+        "cmhd_rk3_step_jvp": (I, [P, P, D, D, P, P, P]),
+        "cmhd_rk3_step_vjp": (I, [P, P, D, D, P, P, P]),
+        "cmhd_bz_plane_vjp": (I, [P, D, P, P]),
         "cmhd_profile_enable": (I, [P, I]),
         "cmhd_profile_read": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "cmhd_last_error": (ctypes.c_char_p, [P]),
@@ -93,6 +98,8 @@ def exported_symbols():
     return ["cmhd_init_grid", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
             "cmhd_set_stream", "cmhd_set_driver", "cmhd_fill_ghosts", "cmhd_rk3_step",
             "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_bz_plane", "cmhd_check_finite",
+            "cmhd_adjoint_workspace_bytes", "cmhd_bind_adjoint_workspace", "cmhd_rk3_step_jvp",
+            "cmhd_rk3_step_vjp", "cmhd_bz_plane_vjp",
             "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy"]
 
 
@@ -243,6 +250,51 @@ class Solver:
             return False
         self._check(rc)
         return True
+
+    # -- differentiation ---------------------------------------------------------
+    def bind_adjoint(self):
+        if getattr(self, "adj_workspace", None) is not None:
+            return
+        nbytes = self.lib.cmhd_adjoint_workspace_bytes(self.ctx)
+        self.adj_workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.adj_workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.cmhd_bind_adjoint_workspace(self.ctx, ctypes.c_void_p(base + off),
+                                                         nbytes))
+
+    def _plane2(self, a):
+        if a is None:
+            return None
+        if (a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous()
+                or tuple(a.shape) != (2, self.grid["ny"], self.grid["nx"])):
+            raise ValueError("driver arrays must be contiguous float64 device tensors [2, ny, nx]")
+        return a
+
+    def rk3_step_jvp(self, x, t, dt, dx, duh=None):
+        """Tangent of one step at x (x's derived ghosts are refreshed)."""
+        self.bind_adjoint()
+        self._stream()
+        dy = torch.zeros_like(x)
+        self._check(self.lib.cmhd_rk3_step_jvp(self.ctx, self._state(x), float(t), float(dt),
+                                               self._state(dx), _ptr(self._plane2(duh)),
+                                               self._state(dy)))
+        return dy
+
+    def rk3_step_vjp(self, x, t, dt, ybar, uhbar=None):
+        """(d step/dx)^T ybar; (d step/du*)^T ybar is added into uhbar."""
+        self.bind_adjoint()
+        self._stream()
+        xbar = torch.zeros_like(x)
+        self._check(self.lib.cmhd_rk3_step_vjp(self.ctx, self._state(x), float(t), float(dt),
+                                               self._state(ybar), self._state(xbar),
+                                               _ptr(self._plane2(uhbar))))
+        return xbar
+
+    def bz_plane_vjp(self, z, bzbar, xbar):
+        self._stream()
+        self._check(self.lib.cmhd_bz_plane_vjp(self.ctx, float(z), _ptr(bzbar.contiguous()),
+                                               self._state(xbar)))
+        return xbar
 
     def profile(self, enable=True):
         self._check(self.lib.cmhd_profile_enable(self.ctx, 1 if enable else 0))

@@ -126,6 +126,8 @@ __global__ void k_fft1d(double2* __restrict__ data, int n, int logn, long long s
   for (int i = threadIdx.x; i < n; i += blockDim.x) data[base + i * stride] = buf[i];
 }
 
+}  // namespace
+
 // forward (sign -1) or inverse (+1) 2-D transform of nplanes planes [ny][nx]
 hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStream_t s) {
   const int nx = p.nx, ny = p.ny;
@@ -141,12 +143,7 @@ hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStre
   return hipGetLastError();
 }
 
-__device__ __forceinline__ double kabs(const KParams& p, int ix, int iy) {
-  const int mx = ix < p.nx / 2 ? ix : ix - p.nx;
-  const int my = iy < p.ny / 2 ? iy : iy - p.ny;
-  const double kx = TWO_PI * mx / p.Lx, ky = TWO_PI * my / p.Ly;
-  return sqrt(kx * kx + ky * ky);
-}
+namespace {
 
 // complex planes: 0 = Ax + i Ay (bottom), 1 = Az (bottom), 2 = Ax + i Ay (top), 3 = Az (top)
 __global__ void k_pack_boundary_planes(const KParams p, const double* __restrict__ f,

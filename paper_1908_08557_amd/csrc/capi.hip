@@ -26,6 +26,9 @@ struct cmhd_ctx {
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
   std::string err;
+  // adjoint workspace
+  char* aws = nullptr;
+  double *Q = nullptr, *Qb = nullptr, *XB = nullptr, *dFB = nullptr, *RB = nullptr, *Gb = nullptr;
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
   ~cmhd_ctx() {
@@ -425,6 +428,147 @@ cmhd_status cmhd_check_finite(cmhd_ctx* c, const double* state) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_check(c, e, "finite check");
   return h ? fail(c, CMHD_ENONFINITE, "state holds a non-finite value") : CMHD_OK;
+}
+
+namespace {
+
+size_t adj_layout(const cmhd_ctx* c, size_t off[8]) {
+  const size_t nzone = size_t(c->grid.nx) * size_t(c->grid.ny) * size_t(c->grid.nz);
+  const size_t qb = align256(NQ_POINT * nzone * sizeof(double));
+  const size_t sb = align256(state_elems(c->grid) * sizeof(double));
+  size_t o = 0;
+  off[0] = o; o += qb;   // Q
+  off[1] = o; o += qb;   // Qbar / dQ
+  off[2] = o; o += sb;   // XB / dX
+  off[3] = o; o += sb;   // dFB / dDF
+  off[4] = o; o += sb;   // RB / dR
+  off[5] = o; o += sb;   // Gbar
+  return o;
+}
+
+cmhd_status need_adj(cmhd_ctx* c) {
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  if (!c->aws) return fail(c, CMHD_ESTATE, "no adjoint workspace bound");
+  return CMHD_OK;
+}
+
+// forward substage s from src to dst (fills the ghosts of src first)
+cmhd_status fwd_stage(cmhd_ctx* c, int s, double* src, double* dst, double t, double dt) {
+  cmhd_status st = do_fill(c, src);
+  if (st != CMHD_OK) return st;
+  StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, t + RK_C[s] * dt)};
+  hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, s, src, dst, c->dF, c->uh, c->ah, a, c->stream);
+  if (e == hipSuccess && c->kp.solar)
+    e = launch_ghost_rows(c->kp, src, dst, c->dF, c->uh, a, s > 0, s < 2, c->stream);
+  return hip_check(c, e, "forward substage");
+}
+
+}  // namespace
+
+size_t cmhd_adjoint_workspace_bytes(const cmhd_ctx* c) {
+  if (!c) return 0;
+  size_t off[8];
+  return adj_layout(c, off);
+}
+
+cmhd_status cmhd_bind_adjoint_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return CMHD_EINVAL;
+  size_t off[8];
+  const size_t need = adj_layout(c, off);
+  if (!dev_ptr) return fail(c, CMHD_EINVAL, "adjoint workspace pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0)
+    return fail(c, CMHD_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (bytes < need) return fail(c, CMHD_EWORKSPACE, "adjoint workspace too small");
+  c->aws = static_cast<char*>(dev_ptr);
+  c->Q = reinterpret_cast<double*>(c->aws + off[0]);
+  c->Qb = reinterpret_cast<double*>(c->aws + off[1]);
+  c->XB = reinterpret_cast<double*>(c->aws + off[2]);
+  c->dFB = reinterpret_cast<double*>(c->aws + off[3]);
+  c->RB = reinterpret_cast<double*>(c->aws + off[4]);
+  c->Gb = reinterpret_cast<double*>(c->aws + off[5]);
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_rk3_step_jvp(cmhd_ctx* c, double* x, double t, double dt, const double* dx,
+                              const double* duh, double* dy) {
+  if (!c || !x || !dx || !dy || !(dt > 0.0)) return CMHD_EINVAL;
+  cmhd_status st = need_adj(c);
+  if (st != CMHD_OK) return st;
+  const KParams& p = c->kp;
+  hipStream_t s = c->stream;
+  const size_t sbytes = state_elems(c->grid) * sizeof(double);
+  double* X[3] = {x, c->W1, c->W2};
+  double* DX = c->XB;
+  double* DDF = c->dFB;
+  double* DR = c->RB;
+  hipError_t e = launch_copy_state_entries(p, dx, DX, s);
+  if (e == hipSuccess) e = hipMemsetAsync(DDF, 0, sbytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(DR, 0, sbytes, s);
+  if (e != hipSuccess) return hip_check(c, e, "jvp init");
+  st = do_fill(c, x);
+  if (st != CMHD_OK) return st;
+  for (int k = 0; k < 3; ++k) {
+    const double rs = ramp(c, t + RK_C[k] * dt);
+    e = launch_fill_lin(p, X[k], DX, c->fft, s);
+    if (e == hipSuccess) e = launch_point_q(p, X[k], c->Q, s);
+    if (e == hipSuccess) e = launch_point_q(p, DX, c->Qb, s);
+    if (e == hipSuccess) e = launch_point_jvp(p, c->Q, c->Qb, c->uh, c->ah, duh, rs, DR, s);
+    if (e == hipSuccess && p.solar) e = launch_ghost_rows_jvp(p, DX, duh, rs, DR, s);
+    if (e == hipSuccess) e = launch_tlm_combine(p, RK_ALPHA[k], RK_BETA[k], dt, DR, DDF, DX, s);
+    if (e != hipSuccess) return hip_check(c, e, "jvp substage");
+    if (k < 2) {
+      st = fwd_stage(c, k, X[k], X[k + 1], t, dt);
+      if (st != CMHD_OK) return st;
+      st = do_fill(c, X[k + 1]);
+      if (st != CMHD_OK) return st;
+    }
+  }
+  return hip_check(c, launch_copy_state_entries(p, DX, dy, s), "jvp output");
+}
+
+cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* c, double* x, double t, double dt, const double* ybar,
+                              double* xbar, double* uhbar) {
+  if (!c || !x || !ybar || !xbar || !(dt > 0.0)) return CMHD_EINVAL;
+  cmhd_status st = need_adj(c);
+  if (st != CMHD_OK) return st;
+  const KParams& p = c->kp;
+  hipStream_t s = c->stream;
+  const size_t sbytes = state_elems(c->grid) * sizeof(double);
+  double* X[3] = {x, c->W1, c->W2};
+  // forward substages 1 and 2: the linearisation points, ghost-filled
+  st = fwd_stage(c, 0, X[0], X[1], t, dt);
+  if (st == CMHD_OK) st = fwd_stage(c, 1, X[1], X[2], t, dt);
+  if (st == CMHD_OK) st = do_fill(c, X[2]);
+  if (st != CMHD_OK) return st;
+  // uhbar may be NULL: accumulate into the Gbar buffer's first planes then drop
+  double* uhb = uhbar ? uhbar : c->Gb;
+  hipError_t e = launch_copy_state_entries(p, ybar, c->XB, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->dFB, 0, sbytes, s);
+  if (e != hipSuccess) return hip_check(c, e, "vjp init");
+  for (int k = 2; k >= 0; --k) {
+    const double rs = ramp(c, t + RK_C[k] * dt);
+    e = launch_adj_combine(p, RK_ALPHA[k], RK_BETA[k], dt, c->XB, c->dFB, c->RB, s);
+    if (e == hipSuccess) e = launch_point_q(p, X[k], c->Q, s);
+    if (e == hipSuccess) e = launch_point_vjp(p, c->Q, c->RB, c->uh, c->ah, rs, c->Qb, uhb, s);
+    if (e == hipSuccess) e = launch_stencil_T(p, c->Qb, c->Gb, s);
+    if (e == hipSuccess) e = launch_fold_ghosts_T(p, X[k], c->Gb, c->XB, c->fft, s);
+    if (e == hipSuccess && p.solar) e = launch_ghost_rows_vjp(p, c->RB, rs, c->XB, uhb, s);
+    if (e != hipSuccess) return hip_check(c, e, "vjp substage");
+    if (!uhbar) {   // the scratch use of Gbar must not leak into the next substage
+      e = hipMemsetAsync(c->Gb, 0, 2 * size_t(p.splane) * sizeof(double), s);
+      if (e != hipSuccess) return hip_check(c, e, "vjp scratch");
+    }
+  }
+  return hip_check(c, launch_copy_state_entries(p, c->XB, xbar, s), "vjp output");
+}
+
+cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* c, double z, const double* bzbar, double* xbar) {
+  if (!c || !bzbar || !xbar) return CMHD_EINVAL;
+  const KParams& p = c->kp;
+  if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
+    return fail(c, CMHD_EINVAL, "z outside the interior");
+  return hip_check(c, launch_bz_plane_vjp(p, z, bzbar, xbar, c->stream), "bz_plane_vjp launch");
 }
 
 cmhd_status cmhd_profile_enable(cmhd_ctx* c, int enable) {

@@ -73,6 +73,47 @@ hipError_t launch_bz_plane(const KParams& p, const double* f, double zq, double*
 hipError_t launch_finite_check(const KParams& p, const double* f, int* flag, hipStream_t s);
 hipError_t launch_sum_abs(const KParams& p, const double* plane, double* out2, hipStream_t s);
 
+// tangent-linear and adjoint pieces (adjoint.hip); Q holds the 72 pointwise
+// inputs of every interior zone, [72][nz*ny*nx]
+constexpr int NQ_POINT = 72;
+hipError_t launch_point_q(const KParams& p, const double* g, double* Q, hipStream_t s);
+hipError_t launch_point_jvp(const KParams& p, const double* Q, const double* dQ, const double* uh,
+                            const double* ah, const double* duh, double ramp, double* dR,
+                            hipStream_t s);
+hipError_t launch_ghost_rows_jvp(const KParams& p, const double* dX, const double* duh,
+                                 double ramp, double* dR, hipStream_t s);
+hipError_t launch_point_vjp(const KParams& p, const double* Q, const double* Rbar,
+                            const double* uh, const double* ah, double ramp, double* Qbar,
+                            double* uhbar, hipStream_t s);
+hipError_t launch_ghost_rows_vjp(const KParams& p, const double* Rbar, double ramp, double* Xbar,
+                                 double* uhbar, hipStream_t s);
+hipError_t launch_stencil_T(const KParams& p, const double* Qbar, double* Gbar, hipStream_t s);
+hipError_t launch_fill_lin(const KParams& p, const double* g, double* dg, double2* scratch,
+                           hipStream_t s);
+hipError_t launch_fold_ghosts_T(const KParams& p, const double* g, const double* Gbar,
+                                double* Xbar, double2* scratch, hipStream_t s);
+hipError_t launch_tlm_combine(const KParams& p, double alpha, double beta, double dt,
+                              const double* dR, double* dDF, double* dX, hipStream_t s);
+hipError_t launch_adj_combine(const KParams& p, double alpha, double beta, double dt, double* Xb,
+                              double* dFb, double* Rb, hipStream_t s);
+hipError_t launch_copy_state_entries(const KParams& p, const double* src, double* dst,
+                                     hipStream_t s);
+hipError_t launch_bz_plane_vjp(const KParams& p, double zq, const double* bzbar, double* Xbar,
+                               hipStream_t s);
+
+// 2-D FFT of nplanes complex planes [ny][nx] in place: sign -1 forward
+// (unnormalised), +1 inverse (unnormalised; the filters carry 1/(nx ny)).
+hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStream_t s);
+
+// |k| of the Fourier mode at index (ix, iy) (FFT order, Nyquist at -n/2)
+__device__ __forceinline__ double kabs(const KParams& p, int ix, int iy) {
+  const int mx = ix < p.nx / 2 ? ix : ix - p.nx;
+  const int my = iy < p.ny / 2 ? iy : iy - p.ny;
+  const double kx = 6.283185307179586476925286766559 * mx / p.Lx;
+  const double ky = 6.283185307179586476925286766559 * my / p.Ly;
+  return sqrt(kx * kx + ky * ky);
+}
+
 // Scratch of the Fourier boundary: complex planes needed by
 // launch_potential_ghosts (4 forward + 12 filtered).
 constexpr int FFT_PLANES = 16;
