@@ -62,8 +62,8 @@ typedef enum { CMHD_ZBC_PERIODIC = 0, CMHD_ZBC_SOLAR = 1 } cmhd_zbc;
 
 typedef struct cmhd_ctx cmhd_ctx;
 
-/* Grid.  nx, ny: powers of two >= 8 (the Fourier boundary and the tiles need
- * them), nz >= 7 (solar) or >= 8 (periodic), nx and ny multiples of 16.
+/* Grid.  nx, ny: powers of two in [16, 1024] (the Fourier boundary works on
+ * power-of-two rows of at most 1024 points; the tiles are 16 x 16), nz >= 8.
  * dx = Lx/nx, dy = Ly/ny.  Solar z is vertex-centred: dz = (z1-z0)/(nz-1),
  * z_0 = z0 is the photosphere and z_{nz-1} = z1 the top boundary point (the
  * boundary layers j = 0 of Sect. 2.3 and nz of Sect. 4.1).  Periodic z:
@@ -214,13 +214,18 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* ctx, double* x, double t, double dt, con
  * z (the loss of a magnetogram fit at that height). */
 cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* ctx, double z, const double* bzbar, double* xbar);
 
-/* Kernel timing.  While enabled, cmhd_rk3_step records a pair of HIP events
- * on the context stream around every launch of the fused substage kernel.
- * cmhd_profile_read synchronises the stream, returns the summed duration in
- * milliseconds and the number of launches since the last read, and resets
- * them.  Enabling and disabling keep pending records. */
+/* Kernel timing.  While enabled, every substage (cmhd_rk3_step,
+ * cmhd_eval_rhs and the forward recomputation of the adjoint) records a pair
+ * of HIP events on the context stream around each launch of the two kernels
+ * selected by cmhd_prof_kernel: the fused stencil/RHS/RK kernel and the
+ * z-derivative pass that precedes it.  cmhd_profile_read synchronises the
+ * stream, returns for the selected kernel the summed duration in milliseconds
+ * and the number of launches since its last read, and resets them; an
+ * unknown selector is CMHD_EINVAL.  Enabling and disabling keep pending
+ * records. */
+typedef enum { CMHD_PROF_SUBSTAGE = 0, CMHD_PROF_ZDERIV = 1 } cmhd_prof_kernel;
 cmhd_status cmhd_profile_enable(cmhd_ctx* ctx, int enable);
-cmhd_status cmhd_profile_read(cmhd_ctx* ctx, double* ms, int* launches);
+cmhd_status cmhd_profile_read(cmhd_ctx* ctx, int which, double* ms, int* launches);
 
 const char* cmhd_last_error(const cmhd_ctx* ctx);
 void cmhd_destroy(cmhd_ctx* ctx);

@@ -81,7 +81,7 @@ def load():
         "cmhd_rk3_step_vjp": (I, [P, P, D, D, P, P, P]),
         "cmhd_bz_plane_vjp": (I, [P, D, P, P]),
         "cmhd_profile_enable": (I, [P, I]),
-        "cmhd_profile_read": (I, [P, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "cmhd_profile_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "cmhd_last_error": (ctypes.c_char_p, [P]),
         "cmhd_destroy": (None, [P]),
     }
@@ -299,11 +299,13 @@ class Solver:
     def profile(self, enable=True):
         self._check(self.lib.cmhd_profile_enable(self.ctx, 1 if enable else 0))
 
-    def profile_read(self):
-        """(total ms, launches) of the fused substage kernel since the last read."""
+    def profile_read(self, which="substage"):
+        """(total ms, launches) since the last read of the fused substage
+        kernel ("substage") or of the z-derivative pass ("zderiv")."""
+        sel = {"substage": 0, "zderiv": 1}[which]
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int(0)
-        self._check(self.lib.cmhd_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        self._check(self.lib.cmhd_profile_read(self.ctx, sel, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
     def close(self):

@@ -12,28 +12,10 @@
 // written out here.  Correctness, not speed, is the target of these kernels.
 #include "cmhd_internal.h"
 #include "dual.h"
+#include "qslots.h"
 #include "rhs_point.h"
 
 namespace cmhd {
-
-constexpr int NQ = 72;
-__host__ __device__ constexpr int q_v(int f) { return f; }
-__host__ __device__ constexpr int q_d(int f, int d) { return 8 + 3 * f + d; }
-constexpr int Q_LAPR = 71;
-// slot of the second derivative (Hessian slot s) of field f, or -1
-__host__ __device__ inline int q_h(int f, int s) {
-  if (f <= AZ) return 32 + 6 * f + s;
-  if (f <= UZ) {
-    const int c = f - UX;
-    if (s <= 2) return 50 + 5 * c + s;
-    // mixed slots of grad div u: u_x xy xz, u_y xy yz, u_z xz yz
-    if (c == 0) return s == 3 ? 53 : (s == 4 ? 54 : -1);
-    if (c == 1) return s == 3 ? 58 : (s == 5 ? 59 : -1);
-    return s == 4 ? 63 : (s == 5 ? 64 : -1);
-  }
-  if (f == LT) return 65 + s;
-  return -1;
-}
 
 namespace {
 
@@ -129,7 +111,7 @@ __global__ __launch_bounds__(128) void k_point_q(const KParams p, const double* 
 // pointwise inputs from the Q buffer as dual numbers: tangent from dQ (JVP)
 // or a unit seed in one slot (one column of the pointwise Jacobian)
 struct QSource {
-  static constexpr int kUnroll = 3;
+  static constexpr int kUnrollA = 3, kUnrollU = 3;
   const double* Q;
   const double* dQ;   // may be null
   long long nzone, z;

@@ -25,14 +25,17 @@ struct cmhd_ctx {
   double* ah = nullptr;   // A_h* target    [2][ny][nx]
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
+  void* dz = nullptr;     // z derivatives of the substage input [16][nz][ny][nx]
   std::string err;
   // adjoint workspace
   char* aws = nullptr;
   double *Q = nullptr, *Qb = nullptr, *XB = nullptr, *dFB = nullptr, *RB = nullptr, *Gb = nullptr;
   bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+  // per timed kernel (CMHD_PROF_*): event pairs recorded and not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2], ev_free;
   ~cmhd_ctx() {
-    for (auto& e : ev_pending) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& v : ev_pending)
+      for (auto& e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   }
 };
@@ -68,6 +71,7 @@ size_t ws_layout(const cmhd_ctx* c, size_t off[8]) {
   off[4] = o; o += align256(2 * plane * sizeof(double));         // ah
   off[5] = o; o += align256(FFT_PLANES * plane * sizeof(double2));  // fft
   off[6] = o; o += 256;                                          // reductions
+  off[7] = o; o += align256(zderiv_bytes(c->kp, c->grid.prec));  // z derivatives
   return o;
 }
 
@@ -271,6 +275,7 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->ah = reinterpret_cast<double*>(c->ws + off[4]);
   c->fft = reinterpret_cast<double2*>(c->ws + off[5]);
   c->red = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
+  c->dz = c->ws + off[7];
   // driver targets start at zero; the stage buffers are fully written before use
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
   hipError_t e = hipMemsetAsync(c->uh, 0, 2 * plane * sizeof(double), c->stream);
@@ -331,6 +336,45 @@ cmhd_status cmhd_cfl_dt(cmhd_ctx* c, double* state, double* dt_out) {
   return do_cfl(c, state, dt_out);
 }
 
+// event pair for one timed launch of kernel `which` (or none when not profiling)
+hipError_t ev_begin(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev) {
+  ev = {nullptr, nullptr};
+  if (!c->profiling) return hipSuccess;
+  if (!c->ev_free.empty()) {
+    ev = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e == hipSuccess) e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(ev.first, c->stream);
+}
+
+hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which) {
+  if (!c->profiling) return hipSuccess;
+  hipError_t e = hipEventRecord(ev.second, c->stream);
+  c->ev_pending[which].push_back(ev);
+  return e;
+}
+
+// one substage from src to dst (ghosts of src already filled): z-derivative
+// pass, fused stencil/RHS/RK kernel, nudged ghost rows
+hipError_t substage(cmhd_ctx* c, int s, const double* src, double* dst, double* dF,
+                    const StageArgs& a) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  hipError_t e = ev_begin(c, ev);
+  if (e == hipSuccess) e = launch_zderiv(c->kp, c->grid.prec, src, c->dz, c->stream);
+  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_ZDERIV);
+  if (e == hipSuccess) e = ev_begin(c, ev);
+  if (e == hipSuccess)
+    e = launch_rhs_rk(c->kp, c->grid.prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, c->stream);
+  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_SUBSTAGE);
+  if (e == hipSuccess && c->kp.solar)
+    e = launch_ghost_rows(c->kp, src, dst, dF, c->uh, a, s > 0, s < 2, c->stream);
+  return e;
+}
+
 cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, double* dt_used) {
   if (!c || !state || !t) return CMHD_EINVAL;
   cmhd_status st = need_ws(c);
@@ -345,25 +389,7 @@ cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, doub
     st = do_fill(c, src[s]);
     if (st != CMHD_OK) return st;
     StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, *t + RK_C[s] * dt)};
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (c->profiling) {
-      if (!c->ev_free.empty()) {
-        ev = c->ev_free.back();
-        c->ev_free.pop_back();
-      } else if (hipEventCreate(&ev.first) != hipSuccess ||
-                 hipEventCreate(&ev.second) != hipSuccess) {
-        return fail(c, CMHD_EDEVICE, "event creation failed");
-      }
-      (void)hipEventRecord(ev.first, c->stream);
-    }
-    hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, s, src[s], dst[s], c->dF, c->uh, c->ah, a,
-                                 c->stream);
-    if (c->profiling) {
-      (void)hipEventRecord(ev.second, c->stream);
-      c->ev_pending.push_back(ev);
-    }
-    if (e == hipSuccess && c->kp.solar)
-      e = launch_ghost_rows(c->kp, src[s], dst[s], c->dF, c->uh, a, s > 0, s < 2, c->stream);
+    hipError_t e = substage(c, s, src[s], dst[s], c->dF, a);
     if (e != hipSuccess) return hip_check(c, e, "rk3 substage launch");
   }
   *t += dt;
@@ -379,11 +405,7 @@ cmhd_status cmhd_eval_rhs(cmhd_ctx* c, double* state, double t, double* rhs) {
   if (st != CMHD_OK) return st;
   // one substage with alpha = 0, beta = 0, dt = 1: dF = RHS, f_next = f (into W1)
   StageArgs a{0.0, 0.0, 1.0, ramp(c, t)};
-  hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, 0, state, c->W1, rhs, c->uh, c->ah, a,
-                               c->stream);
-  if (e == hipSuccess && c->kp.solar)
-    e = launch_ghost_rows(c->kp, state, c->W1, rhs, c->uh, a, 0, 1, c->stream);
-  return hip_check(c, e, "eval_rhs launch");
+  return hip_check(c, substage(c, 0, state, c->W1, rhs, a), "eval_rhs launch");
 }
 
 cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, double* dst,
@@ -458,10 +480,7 @@ cmhd_status fwd_stage(cmhd_ctx* c, int s, double* src, double* dst, double t, do
   cmhd_status st = do_fill(c, src);
   if (st != CMHD_OK) return st;
   StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, t + RK_C[s] * dt)};
-  hipError_t e = launch_rhs_rk(c->kp, c->grid.prec, s, src, dst, c->dF, c->uh, c->ah, a, c->stream);
-  if (e == hipSuccess && c->kp.solar)
-    e = launch_ghost_rows(c->kp, src, dst, c->dF, c->uh, a, s > 0, s < 2, c->stream);
-  return hip_check(c, e, "forward substage");
+  return hip_check(c, substage(c, s, src, dst, c->dF, a), "forward substage");
 }
 
 }  // namespace
@@ -577,20 +596,22 @@ cmhd_status cmhd_profile_enable(cmhd_ctx* c, int enable) {
   return CMHD_OK;
 }
 
-cmhd_status cmhd_profile_read(cmhd_ctx* c, double* ms, int* launches) {
+cmhd_status cmhd_profile_read(cmhd_ctx* c, int which, double* ms, int* launches) {
   if (!c || !ms || !launches) return CMHD_EINVAL;
+  if (which != CMHD_PROF_SUBSTAGE && which != CMHD_PROF_ZDERIV)
+    return fail(c, CMHD_EINVAL, "unknown kernel selector");
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_check(c, e, "profile sync");
   double sum = 0.0;
-  for (auto& ev : c->ev_pending) {
+  for (auto& ev : c->ev_pending[which]) {
     float t = 0.0f;
     e = hipEventElapsedTime(&t, ev.first, ev.second);
     if (e != hipSuccess) return hip_check(c, e, "event elapsed");
     sum += t;
     c->ev_free.push_back(ev);
   }
-  *launches = int(c->ev_pending.size());
-  c->ev_pending.clear();
+  *launches = int(c->ev_pending[which].size());
+  c->ev_pending[which].clear();
   *ms = sum;
   return CMHD_OK;
 }

@@ -54,9 +54,13 @@ constexpr double RK_BETA[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 constexpr double RK_C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
 
 // Launchers (each returns the hipError_t of its launch).
-hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, double* fo,
-                         double* dF, const double* uh, const double* ah, StageArgs st,
-                         hipStream_t s);
+// bytes of the z-derivative buffer (16 slots of nz planes, in the precision
+// of the right-hand side)
+size_t zderiv_bytes(const KParams& p, int prec);
+hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, hipStream_t s);
+hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, const void* dz,
+                         double* fo, double* dF, const double* uh, const double* ah,
+                         StageArgs st, hipStream_t s);
 hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,
                              const double* uh, StageArgs st, int read_dF, int write_dF,
                              hipStream_t s);

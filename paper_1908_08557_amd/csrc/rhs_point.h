@@ -26,7 +26,13 @@
 //
 // Source interface (f a field index, slot a Hessian slot xx yy zz xy xz yz):
 //   S v(f); double v64(f); S d(f, dir); S h(f, slot); S lapr();
+//   kUnrollA, kUnrollU: unroll factors of the component loops over A and u
+//   (1 keeps a source's on-demand reads in a rolled loop).
 // h(f, slot) is only asked for the slots the equations use.
+//
+// The evaluation is split into a magnetic part (the only one that reads A's
+// derivatives) and a fluid part, so that a kernel can release its staged
+// copy of A between the two; rhs_eval runs both.
 #pragma once
 
 #include <type_traits>
@@ -65,10 +71,17 @@ __host__ __device__ inline int rad_segment(const KParams& p, double x) {
 
 #define CMHD_FENCE() __builtin_amdgcn_sched_barrier(0)
 
+// what the fluid part needs of the magnetic part
+template <typename S>
+struct MagState {
+  S b[3], iBn;     // field direction and 1/|B|_r (Spitzer)
+  S vv[3], sbb;    // b_i d_i B_j and b.vv (Spitzer curvature terms)
+  S JxB[3], ohm;   // Lorentz force, eta mu0 J^2 / mu0
+};
+
 template <typename S, class Src>
-__device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
-                                         const KParams& p, S out[NF]) {
-  constexpr bool kFloat = std::is_same<S, float>::value;
+__device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& pc,
+                                             const KParams& p, S out[NF], MagState<S>& m) {
   const S w = S(pc.w), dw = S(pc.dw);
   const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
 
@@ -91,7 +104,7 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
     for (int j = 0; j < 3; ++j) dB[i][j] = S(0.0);
   // a rolled loop over the components when the source allows it: each
   // component's stencil reads then form their own scheduling region
-#pragma unroll(Src::kUnroll)
+#pragma unroll(Src::kUnrollA)
   for (int c = 0; c < 3; ++c) {
     S h[6];
 #pragma unroll
@@ -131,7 +144,27 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
   const S J[3] = {cB[0] * S(p.inv_mu0), cB[1] * S(p.inv_mu0), cB[2] * S(p.inv_mu0)};
   const S JxB[3] = {J[1] * B[2] - J[2] * B[1], J[2] * B[0] - J[0] * B[2],
                     J[0] * B[1] - J[1] * B[0]};
-  CMHD_FENCE();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    m.b[i] = b[i];
+    m.vv[i] = vv[i];
+    m.JxB[i] = JxB[i];
+  }
+  m.iBn = iBn;
+  m.sbb = sbb;
+  m.ohm = ohm;
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
+                                          const KParams& p, const MagState<S>& m, S out[NF]) {
+  constexpr bool kFloat = std::is_same<S, float>::value;
+  const S w = S(pc.w);
+  const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
+  const S* JxB = m.JxB;
+  const S* b = m.b;
+  const S* vv = m.vv;
+  const S iBn = m.iBn, sbb = m.sbb, ohm = m.ohm;
 
   // ================= momentum ===============================================
   S rho, T;
@@ -169,7 +202,7 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
     // Laplacian of u_c and grad div u (mixed slots: xy, xz for u_x; xy, yz
     // for u_y; xz, yz for u_z)
     S lapu[3], gd[3] = {S(0.0), S(0.0), S(0.0)};
-#pragma unroll(Src::kUnroll)
+#pragma unroll(Src::kUnrollU)
     for (int c = 0; c < 3; ++c) {
       const S hxx = src.h(UX + c, 0), hyy = src.h(UX + c, 1), hzz = src.h(UX + c, 2);
       const S lap = hxx + hyy + hzz;
@@ -272,6 +305,15 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
     out[LR] = S(0.0);
   }
   if (pc.top) out[UZ] = S(0.0);
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
+                                         const KParams& p, S out[NF]) {
+  MagState<S> m;
+  rhs_magnetic<S>(src, pc, p, out, m);
+  CMHD_FENCE();
+  rhs_fluid<S>(src, pc, p, m, out);
 }
 
 }  // namespace cmhd
