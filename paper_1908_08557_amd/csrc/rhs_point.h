@@ -61,11 +61,22 @@ __device__ inline float s_exp(float a) { return expf(a); }
 __device__ inline double s_sqrt(double a) { return sqrt(a); }
 __device__ inline float s_sqrt(float a) { return __fsqrt_rn(a); }
 
+// The radiative-loss table (breakpoints ln T_i, values ln Lambda_i and the
+// slopes between them) as read from the kernel parameters; a kernel may pass
+// an accessor of its own copy instead (same interface).
+struct ParamRadTable {
+  const KParams& p;
+  __device__ __forceinline__ double lnT(int i) const { return p.rad_lnT[i]; }
+  __device__ __forceinline__ double lnL(int i) const { return p.rad_lnL[i]; }
+  __device__ __forceinline__ double slope(int i) const { return p.rad_slope[i]; }
+};
+
 // continuous piecewise-linear ln Lambda(ln T): segment index (constant
 // outside the table, handled by the caller)
-__host__ __device__ inline int rad_segment(const KParams& p, double x) {
+template <class Tab>
+__device__ __forceinline__ int rad_segment(const Tab& t, int n, double x) {
   int i = 0;
-  for (int j = 1; j < p.n_rad - 1; ++j) i = (x >= p.rad_lnT[j]) ? j : i;
+  for (int j = 1; j < n - 1; ++j) i = (x >= t.lnT(j)) ? j : i;
   return i;
 }
 
@@ -155,9 +166,48 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   m.ohm = ohm;
 }
 
+// optically thin loss Q_rad/(rho c_v T) = exp(ln rho + lnL(ln T) - ln T) W(ln T) / c_v
+// (the only table lookup of the right-hand side; a kernel may evaluate it
+// early, before it starts memory traffic that the lookup must not wait on)
+template <typename S, class Src, class Tab>
+__device__ __forceinline__ S rhs_radiation(const Src& src, const KParams& p, const Tab& tab) {
+  constexpr bool kFloat = std::is_same<S, float>::value;
+  S rad = S(0.0);
+  if (p.n_rad > 0) {
+    const double x = src.v64(LT);
+    if (x > p.lnT_rad_lo) {
+      const int n = p.n_rad;
+      const int i = rad_segment(tab, n, x);
+      const bool below = x < tab.lnT(0), above = x >= tab.lnT(n - 1);
+      S wc;
+      if (x >= p.lnT_rad_hi) {
+        wc = S(1.0);
+      } else {
+        const S s = (src.v(LT) - S(p.lnT_rad_lo)) * S(p.inv_dlnT_rad);
+        wc = s * s * (S(3.0) - S(2.0) * s);
+      }
+      S ex;
+      if constexpr (kFloat) {
+        const double lnL64 = below ? tab.lnL(0)
+                             : above ? tab.lnL(n - 1)
+                                     : tab.lnL(i) + tab.slope(i) * (x - tab.lnT(i));
+        ex = float(src.v64(LR) + lnL64 - x);
+      } else {
+        const S lnL = below   ? S(tab.lnL(0))
+                      : above ? S(tab.lnL(n - 1))
+                              : S(tab.lnL(i)) + S(tab.slope(i)) * (src.v(LT) - S(tab.lnT(i)));
+        ex = src.v(LR) + lnL - src.v(LT);
+      }
+      rad = s_exp(ex) * wc * S(1.0 / p.cv);
+    }
+  }
+  return rad;
+}
+
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
-                                          const KParams& p, const MagState<S>& m, S out[NF]) {
+                                          const KParams& p, const MagState<S>& m, S rad,
+                                          S out[NF]) {
   constexpr bool kFloat = std::is_same<S, float>::value;
   const S w = S(pc.w);
   const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
@@ -261,35 +311,6 @@ __device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
     }
   }
 
-  // optically thin loss: Q_rad/(rho c_v T) = exp(ln rho + lnL(ln T) - ln T) W(ln T) / c_v
-  S rad = S(0.0);
-  if (p.n_rad > 0) {
-    const double x = src.v64(LT);
-    if (x > p.lnT_rad_lo) {
-      const int i = rad_segment(p, x);
-      const bool below = x < p.rad_lnT[0], above = x >= p.rad_lnT[p.n_rad - 1];
-      S wc;
-      if (x >= p.lnT_rad_hi) {
-        wc = S(1.0);
-      } else {
-        const S s = (src.v(LT) - S(p.lnT_rad_lo)) * S(p.inv_dlnT_rad);
-        wc = s * s * (S(3.0) - S(2.0) * s);
-      }
-      S ex;
-      if constexpr (kFloat) {
-        const double lnL64 = below ? p.rad_lnL[0]
-                             : above ? p.rad_lnL[p.n_rad - 1]
-                                     : p.rad_lnL[i] + p.rad_slope[i] * (x - p.rad_lnT[i]);
-        ex = float(src.v64(LR) + lnL64 - x);
-      } else {
-        const S lnL = below   ? S(p.rad_lnL[0])
-                      : above ? S(p.rad_lnL[p.n_rad - 1])
-                              : S(p.rad_lnL[i]) + S(p.rad_slope[i]) * (src.v(LT) - S(p.rad_lnT[i]));
-        ex = src.v(LR) + lnL - src.v(LT);
-      }
-      rad = s_exp(ex) * wc * S(1.0 / p.cv);
-    }
-  }
   {
     const S udT = ux * GlT[0] + uy * GlT[1] + uz * GlT[2];
     out[LT] = heat + cond - rad - udT - S(p.gm1) * divu + S(p.chi_s) * w * lapT;
@@ -311,9 +332,10 @@ template <typename S, class Src>
 __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
                                          const KParams& p, S out[NF]) {
   MagState<S> m;
+  const S rad = rhs_radiation<S>(src, p, ParamRadTable{p});
   rhs_magnetic<S>(src, pc, p, out, m);
   CMHD_FENCE();
-  rhs_fluid<S>(src, pc, p, m, out);
+  rhs_fluid<S>(src, pc, p, m, rad, out);
 }
 
 }  // namespace cmhd

@@ -5,22 +5,26 @@
 // the right-hand side).
 //
 // k_rhs_rk: one thread per (x, y) column of a 16 x 16 tile, marching in z.
-// Every input it needs at plane k is single-plane data, so plane k+1 is
-// staged into LDS by direct global->LDS copies (16-byte lanes, no registers
-// in flight) while plane k is being computed:
+// Every input it needs at plane k is single-plane data, staged into LDS by
+// direct global->LDS copies (16-byte lanes, no registers in flight):
 //   P   the 8 fields on the 22 x 24 haloed plane (x0-4 .. x0+19, y0-3 .. y0+18)
 //   Zs  d/dz of A, u, ln T on the same haloed plane (for the xz, yz mixed
 //       derivatives D1_x D1_z, D1_y D1_z)
 //   Zo  d/dz ln rho and the 8 d2/dz2 at the own columns
 //   DF  the RK register at the own columns (substages 2 and 3)
-// Per plane:
-//   1a  stencils from LDS -> the 72 pointwise inputs q in registers; D1_x of
-//       the six fields with an xy mixed derivative on the tile and its y halo
-//       -> LDS
-//   --  barrier; the copies of plane k+1 (and the RK register of plane k) are
-//       issued
-//   1b  xy mixed derivatives D1_y (D1_x f) from LDS
-//   2   pointwise right-hand side from registers (rhs_eval)
+// each split into the fields of A and the others (separate LDS objects, so
+// that the compiler can tell a read of one from a copy in flight into the
+// other).  Per plane:
+//   1a  stencils -> the pointwise inputs of all fields but A in registers;
+//       D1_x of the six fields with an xy mixed derivative on the tile and its
+//       y halo -> LDS
+//   --  barrier; copies of the RK register of plane k and of the non-A fields
+//       of plane k+1 are issued (their arrays were last read in 1a)
+//   1b  xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
+//   2a  radiative loss (table in LDS) and the magnetic part of the right-hand
+//       side, A's derivatives read from LDS on demand
+//   --  barrier; copies of the A fields of plane k+1 are issued
+//   2b  fluid part of the right-hand side from registers
 //   --  wait for the copies, barrier
 //   3   dF <- alpha dF + dt RHS, f_next <- f + beta dF in float64, stored once
 // The arithmetic of every derivative is that of the product stencils applied
@@ -36,42 +40,61 @@ namespace {
 // haloed plane: RW x RH, x from x0-4 (16-byte aligned rows), y from y0-3
 constexpr int RW = 24, RH = 22, RPL = RW * RH;
 constexpr int DXW = TX, DXH = RH;   // D1_x on the tile columns and all 22 rows
-constexpr int NZS = 7;              // haloed d/dz: A_x A_y A_z u_x u_y u_z ln T
-constexpr int NZO = 9;              // own d/dz ln rho, then d2/dz2 of the 8 fields
+constexpr int DXP = DXW * DXH;
+constexpr int NA = 3;               // fields of A
+constexpr int NN = NF - NA;         // u_x u_y u_z ln rho ln T
+constexpr int NZN = 4;              // haloed d/dz of u_x u_y u_z ln T
+constexpr int NON = 6;              // own d/dz ln rho, d2/dz2 of u_x u_y u_z ln rho ln T
 constexpr int NDX = 6;              // xy mixed: A_x A_y A_z u_x u_y ln T
 constexpr int NZSLOT = 2 * NF;      // slots of the z-derivative buffer
+constexpr int PC = NG * RW + NG;    // own point relative to a haloed-plane base
+constexpr int DC = NG * DXW;        // own point relative to the D1_x base
 
-__device__ __forceinline__ constexpr int zs_index(int f) { return f < LR ? f : (f == LT ? 6 : -1); }
+// haloed d/dz slot of a non-A field, own-column slot of a non-A quantity
+__device__ __forceinline__ constexpr int zn_index(int f) { return f == LT ? 3 : f - UX; }
+__device__ __forceinline__ constexpr int on_d2(int f) { return f - UX + 1; }   // d2/dz2 of u.., ln rho, ln T
 __device__ __forceinline__ constexpr int dx_index(int f) { return f <= UY ? f : (f == LT ? 5 : -1); }
 
-template <typename Real>
-struct Stage {
-  double P[NF][RPL];
-  Real Zs[NZS][RPL];
-  Real Zo[NZO][NT];
-  double Dx[NDX][DXH * DXW];
-  double DF[NF][NT];
-};
-
-template <typename T>
-using lds = __attribute__((address_space(3))) T;
-
-// An LDS pointer the compiler cannot see through, re-made at every plane:
-// every access is then this base plus a small non-negative immediate, and no
-// per-offset addresses are precomputed and held across the plane loop.
-template <typename T>
-__device__ __forceinline__ lds<T>* lds_base(T* p) {
-  lds<T>* q = (lds<T>*)p;
-  asm volatile("" : "+v"(q));
-  return q;
+// An integer the compiler cannot see through, re-made at every plane: array
+// accesses are then a per-array base register plus small non-negative
+// immediates, and no per-offset addresses are precomputed and held across the
+// plane loop.
+__device__ __forceinline__ int opaque(int i) {
+  asm volatile("" : "+v"(i));
+  return i;
 }
 
-// unscaled sixth-order D1 (60 h D1) at index c, stride s
 template <typename Ptr>
 __device__ __forceinline__ auto d1u(Ptr a, int c, int s) {
   using R = typename std::remove_cv<typename std::remove_reference<decltype(a[0])>::type>::type;
   return R(45.0) * (a[c + s] - a[c - s]) - R(9.0) * (a[c + 2 * s] - a[c - 2 * s]) +
          (a[c + 3 * s] - a[c - 3 * s]);
+}
+template <typename Ptr>
+__device__ __forceinline__ double d2u(Ptr a, int c, int s) {
+  return -490.0 * a[c] + 270.0 * (a[c + s] + a[c - s]) - 27.0 * (a[c + 2 * s] + a[c - 2 * s]) +
+         2.0 * (a[c + 3 * s] + a[c - 3 * s]);
+}
+
+// Workgroup barrier for LDS traffic only: this wave's LDS reads and writes
+// are complete, global->LDS copies in flight are not waited for.  The waits
+// are builtins (not asm) so that the compiler's own wait insertion knows
+// about them.  s_waitcnt immediates (gfx9 encoding): lgkmcnt(0) alone is
+// 0xC07F, vmcnt(0) lgkmcnt(0) is 0x0070.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait for this wave's global->LDS copies (and stores), then a barrier: the
+// copies of all waves are visible to all.
+__device__ __forceinline__ void copies_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
 }
 
 // one 16-byte global->LDS copy per lane: lane l of the wave writes
@@ -112,13 +135,15 @@ struct Chunks {
 static_assert(Chunks<8>::HI == 5 && Chunks<8>::OI == 2 && Chunks<4>::HI == 3 &&
                   Chunks<4>::OI == 1, "chunk counts");
 
-// this wave's share of the copies of one plane: wave w issues the chunk
-// groups m = w, w+4, ... of every array
+// This wave's share of the copies of one plane: wave w issues the chunk
+// groups m = w, w+4 of every array.  The lane offset goes through an empty asm
+// so that each address stays a uniform base plus a 32-bit lane offset (no
+// per-lane 64-bit pointers carried across the plane loop).
 template <typename Real>
 struct Copier {
   using CD = Chunks<8>;
   using CR = Chunks<sizeof(Real)>;
-  unsigned hd[2], hr[2], od, orl;   // lane offsets of the wave's groups
+  unsigned hd[2], hr[2], od, orl;
   int w, lane;
   __device__ void init(int w_, int lane_, int x0, int y0, int nx, int ny) {
     w = w_;
@@ -131,63 +156,47 @@ struct Copier {
     orl = CR::own(w, lane, x0, y0, nx);
   }
   template <int E>
-  __device__ void halo_group(const char* base, char* lds, int m, unsigned off) const {
+  __device__ void halo(const void* base, void* lds, unsigned off0, unsigned off1) const {
     using C = Chunks<E>;
-    if (m < C::HI && m * 64 + lane < C::HN) copy16(base + off, lds + m * 1024);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int m = w + 4 * g;
+      unsigned off = g == 0 ? off0 : off1;
+      asm volatile("" : "+v"(off));
+      if (m < C::HI && m * 64 + lane < C::HN)
+        copy16(static_cast<const char*>(base) + off, static_cast<char*>(lds) + m * 1024);
+    }
   }
   template <int E>
-  __device__ void own_group(const char* base, char* lds, int m, unsigned off) const {
+  __device__ void own(const void* base, void* lds, unsigned off) const {
     using C = Chunks<E>;
-    if (m < C::OI && m * 64 + lane < C::ON) copy16(base + off, lds + m * 1024);
+    asm volatile("" : "+v"(off));
+    if (w < C::OI && w * 64 + lane < C::ON)
+      copy16(static_cast<const char*>(base) + off, static_cast<char*>(lds) + w * 1024);
   }
-  // the plane-k inputs: state (array plane k+NG) and z derivatives (plane k)
-  __device__ void plane(Stage<Real>& S, const double* f, const Real* dz, long long sf,
-                        long long sp, long long szs, int k) const {
-#pragma unroll
-    for (int fi = 0; fi < NF; ++fi) {
-      const char* b = reinterpret_cast<const char*>(f + fi * sf + (k + NG) * sp);
-      halo_group<8>(b, reinterpret_cast<char*>(S.P[fi]), w, hd[0]);
-      halo_group<8>(b, reinterpret_cast<char*>(S.P[fi]), w + 4, hd[1]);
-    }
-#pragma unroll
-    for (int fi = 0; fi < NF; ++fi) {
-      if (fi == LR) continue;
-      const char* b = reinterpret_cast<const char*>(dz + fi * szs + k * sp);
-      halo_group<sizeof(Real)>(b, reinterpret_cast<char*>(S.Zs[zs_index(fi)]), w, hr[0]);
-      halo_group<sizeof(Real)>(b, reinterpret_cast<char*>(S.Zs[zs_index(fi)]), w + 4, hr[1]);
-    }
-#pragma unroll
-    for (int s = 0; s < NZO; ++s) {
-      const int slot = s == 0 ? LR : NF + (s - 1);
-      const char* b = reinterpret_cast<const char*>(dz + slot * szs + k * sp);
-      own_group<sizeof(Real)>(b, reinterpret_cast<char*>(S.Zo[s]), w, orl);
-    }
-  }
-  __device__ void rk_register(Stage<Real>& S, const double* dF, long long sf, long long sp,
-                              int k) const {
-#pragma unroll
-    for (int fi = 0; fi < NF; ++fi) {
-      const char* b = reinterpret_cast<const char*>(dF + fi * sf + (k + NG) * sp);
-      own_group<8>(b, reinterpret_cast<char*>(S.DF[fi]), w, od);
-    }
-  }
+};
+
+// The radiative-loss table copied into LDS.
+struct LdsRadTable {
+  const double* t;   // [lnT 16][lnL 16][slope 16]
+  __device__ __forceinline__ double lnT(int i) const { return t[i]; }
+  __device__ __forceinline__ double lnL(int i) const { return t[CMHD_MAX_RAD + i]; }
+  __device__ __forceinline__ double slope(int i) const { return t[2 * CMHD_MAX_RAD + i]; }
 };
 
 // Source for rhs_eval: the derivatives of A are read from the staged plane on
 // demand (rolled component loop, few registers), everything else from the
-// inputs gathered into registers (indices are compile-time constants).
-constexpr int PC = NG * RW + NG;   // own point relative to a haloed-plane base
-constexpr int DC = NG * DXW;       // own point relative to the D1_x base
-
+// inputs gathered into registers (indices are compile-time constants).  The
+// A arrays are addressed from per-plane opaque bases at their lowest address.
 template <typename Real>
 struct HybridSource {
   static constexpr int kUnrollA = 1, kUnrollU = 3;
   const Real* q;
   const double* v64s;
-  lds<double>* pP;
-  lds<Real>* pZ;
-  lds<Real>* pO;
-  lds<double>* pD;
+  const double* pP;   // A fields, haloed plane, based at c - PC
+  const Real* pZ;     // d/dz of A, haloed, based at c - PC
+  const Real* pO;     // d2/dz2 of A, own column
+  const double* pD;   // D1_x, based at cx - DC
   double i60dx, i60dy, i180dx2, i180dy2, ixy;
   __device__ __forceinline__ Real v(int f) const { return q[q_v(f)]; }
   __device__ __forceinline__ double v64(int f) const { return v64s[f]; }
@@ -200,21 +209,10 @@ struct HybridSource {
     if (f <= AZ) {
       const int b = f * RPL + PC;
       switch (s) {
-        case 0: {
-          const double c0 = pP[b];
-          return Real((-490.0 * c0 + 270.0 * (pP[b + 1] + pP[b - 1]) -
-                       27.0 * (pP[b + 2] + pP[b - 2]) + 2.0 * (pP[b + 3] + pP[b - 3])) *
-                      i180dx2);
-        }
-        case 1: {
-          const double c0 = pP[b];
-          return Real((-490.0 * c0 + 270.0 * (pP[b + RW] + pP[b - RW]) -
-                       27.0 * (pP[b + 2 * RW] + pP[b - 2 * RW]) +
-                       2.0 * (pP[b + 3 * RW] + pP[b - 3 * RW])) *
-                      i180dy2);
-        }
-        case 2: return pO[(1 + f) * NT];
-        case 3: return Real(d1u(pD, f * DXH * DXW + DC, DXW) * ixy);
+        case 0: return Real(d2u(pP, b, 1) * i180dx2);
+        case 1: return Real(d2u(pP, b, RW) * i180dy2);
+        case 2: return pO[f * NT];
+        case 3: return Real(d1u(pD, f * DXP + DC, DXW) * ixy);
         case 4: return d1u(pZ, b, 1) * Real(i60dx);
         default: return d1u(pZ, b, RW) * Real(i60dy);
       }
@@ -224,6 +222,35 @@ struct HybridSource {
   }
   __device__ __forceinline__ Real lapr() const { return q[Q_LAPR]; }
 };
+
+// Block -> (tile x, tile y, z chunk).  Blocks are dispatched round-robin to
+// the 8 XCDs (each with its own L2), and the 32 CUs of an XCD run 32 blocks at
+// a time.  With the XCD-aware order, the blocks that one XCD runs together form
+// a compact patch of pw x ph tiles of one z chunk, so that the haloed rows they
+// share (three 128-byte lines per 24-element row) are L2 hits and not
+// separate HBM reads.
+struct TileMap {
+  int ntx, nty, pw, ph, xcd;
+};
+
+__device__ __forceinline__ void tile_of(int id, const TileMap& m, int& bx, int& by, int& bz) {
+  if (m.xcd) {
+    const int np = m.pw * m.ph;
+    const int slot = id >> 3;
+    const int patch = (slot / np) * 8 + (id & 7);
+    const int within = slot - (slot / np) * np;
+    const int ppr = m.ntx / m.pw;
+    const int ppc = ppr * (m.nty / m.ph);
+    bz = patch / ppc;
+    const int r = patch - bz * ppc;
+    bx = (r % ppr) * m.pw + within % m.pw;
+    by = (r / ppr) * m.ph + within / m.pw;
+  } else {
+    bx = id % m.ntx;
+    by = (id / m.ntx) % m.nty;
+    bz = id / (m.ntx * m.nty);
+  }
+}
 
 __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double& dw) {
   w = 0.0;
@@ -279,13 +306,23 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                                double* __restrict__ dF,
                                                const double* __restrict__ uh,
                                                const double* __restrict__ ah, const KParams p,
-                                               const StageArgs st, int kchunk) {
-  __shared__ __align__(16) Stage<Real> S;
-  constexpr bool kFloat = !std::is_same<Real, double>::value;
+                                               const StageArgs st, int kchunk,
+                                               const TileMap tm) {
+  __shared__ __align__(16) double sPA[NA][RPL];   // values of A, haloed
+  __shared__ __align__(16) double sPN[NN][RPL];   // values of u, ln rho, ln T, haloed
+  __shared__ __align__(16) Real sZA[NA][RPL];     // d/dz of A, haloed
+  __shared__ __align__(16) Real sZN[NZN][RPL];    // d/dz of u, ln T, haloed
+  __shared__ __align__(16) Real sOA[NA][NT];      // d2/dz2 of A, own
+  __shared__ __align__(16) Real sON[NON][NT];     // d/dz ln rho, d2/dz2 of the others, own
+  __shared__ __align__(16) double sDx[NDX][DXP];  // D1_x (unscaled) on tile + y halo
+  __shared__ __align__(16) double sDF[NF][NT];    // RK register, own
+  __shared__ __align__(16) double sRad[3 * CMHD_MAX_RAD];
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  int bx, by, bz;
+  tile_of(blockIdx.x, tm, bx, by, bz);
+  const int x0 = bx * TX, y0 = by * TY;
   const long long sp = p.splane, sf = p.sfield, szs = (long long)p.nz * sp;
   const int oc = (y0 + ty) * p.nx + (x0 + tx);    // own column within a plane
   const int c = (ty + NG) * RW + (tx + 4);        // own point in the haloed plane
@@ -293,82 +330,113 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
 
   Copier<Real> cp;
   cp.init(__builtin_amdgcn_readfirstlane(tid / 64), tid % 64, x0, y0, p.nx, p.ny);
+  // copies of plane k: the fields of A (a) or the others
+  auto copy_plane = [&](int k, bool a) {
+    if (a) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        cp.template halo<8>(f + (AX + i) * sf + (k + NG) * sp, sPA[i], cp.hd[0], cp.hd[1]);
+        cp.template halo<sizeof(Real)>(dz + (AX + i) * szs + k * sp, sZA[i], cp.hr[0], cp.hr[1]);
+        cp.template own<sizeof(Real)>(dz + (NF + AX + i) * szs + k * sp, sOA[i], cp.orl);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NN; ++i)
+        cp.template halo<8>(f + (UX + i) * sf + (k + NG) * sp, sPN[i], cp.hd[0], cp.hd[1]);
+#pragma unroll
+      for (int i = 0; i < NZN; ++i) {
+        const int fi = i < 3 ? UX + i : LT;
+        cp.template halo<sizeof(Real)>(dz + fi * szs + k * sp, sZN[i], cp.hr[0], cp.hr[1]);
+      }
+      cp.template own<sizeof(Real)>(dz + LR * szs + k * sp, sON[0], cp.orl);
+#pragma unroll
+      for (int i = 0; i < NN; ++i)
+        cp.template own<sizeof(Real)>(dz + (NF + UX + i) * szs + k * sp, sON[1 + i], cp.orl);
+    }
+  };
 
   // y-halo rows of D1_x computed by threads 0..95: rows 0-2 and 19-21
   const int hrow = tid < 3 * TX ? tid / TX : TY + NG + (tid - 3 * TX) / TX;
   const int hcol = tid % TX;
 
-  const int kbeg = blockIdx.z * kchunk;
+  const int kbeg = bz * kchunk;
   const int kend = min(kbeg + kchunk, p.nz);
 
-  cp.plane(S, f, dz, sf, sp, szs, kbeg);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  if (tid < CMHD_MAX_RAD) {
+    sRad[tid] = p.rad_lnT[tid];
+    sRad[CMHD_MAX_RAD + tid] = p.rad_lnL[tid];
+    sRad[2 * CMHD_MAX_RAD + tid] = p.rad_slope[tid];
+  }
+  copy_plane(kbeg, true);
+  copy_plane(kbeg, false);
+  copies_barrier();
 
   for (int k = kbeg; k < kend; ++k) {
     // ---- 1a: stencils of the staged plane into registers (all but the
-    // derivatives of A, which the magnetic part reads on demand); D1_x of the
-    // xy-mixed fields into LDS.  Bases sit at the lowest address each array
-    // is read at, so that all offsets are non-negative immediates.
-    const auto pP = lds_base(&S.P[0][c - PC]);
-    const auto pZ = lds_base(&S.Zs[0][c - PC]);
-    const auto pO = lds_base(&S.Zo[0][tid]);
-    const auto pD = lds_base(&S.Dx[0][cx - DC]);
+    // derivatives of A); D1_x of the xy-mixed fields into LDS
+    const int ic = opaque(c - PC), icx = opaque(cx - DC), it = opaque(tid);
+    const double* pPA = &sPA[0][0] + ic;
+    const double* pPN = &sPN[0][0] + ic;
+    const Real* pZN = &sZN[0][0] + ic;
+    const Real* pON = &sON[0][0] + it;
+    double* pDx = &sDx[0][0] + icx;
     Real q[NQ];
     double v64[NF];
 #pragma unroll
     for (int fi = 0; fi < NF; ++fi) {
-      const int b = fi * RPL + PC;
+      const double* pP = fi <= AZ ? pPA : pPN;
+      const int b = (fi <= AZ ? fi : fi - UX) * RPL + PC;
       const double c0 = pP[b];
-      const double xm1 = pP[b - 1], xp1 = pP[b + 1], xm2 = pP[b - 2], xp2 = pP[b + 2];
-      const double xm3 = pP[b - 3], xp3 = pP[b + 3];
-      const double d1x = 45.0 * (xp1 - xm1) - 9.0 * (xp2 - xm2) + (xp3 - xm3);
+      const double d1x = d1u(pP, b, 1);
       v64[fi] = c0;
       q[q_v(fi)] = Real(c0);
       q[q_d(fi, 0)] = Real(d1x * p.i60dx);
-      if (dx_index(fi) >= 0) pD[dx_index(fi) * DXH * DXW + DC] = d1x;
+      if (dx_index(fi) >= 0) pDx[dx_index(fi) * DXP + DC] = d1x;
       if (fi > AZ) {
-        const double ym1 = pP[b - RW], yp1 = pP[b + RW], ym2 = pP[b - 2 * RW];
-        const double yp2 = pP[b + 2 * RW], ym3 = pP[b - 3 * RW], yp3 = pP[b + 3 * RW];
-        const double d1y = 45.0 * (yp1 - ym1) - 9.0 * (yp2 - ym2) + (yp3 - ym3);
-        const double d2x =
-            -490.0 * c0 + 270.0 * (xp1 + xm1) - 27.0 * (xp2 + xm2) + 2.0 * (xp3 + xm3);
-        const double d2y =
-            -490.0 * c0 + 270.0 * (yp1 + ym1) - 27.0 * (yp2 + ym2) + 2.0 * (yp3 + ym3);
-        q[q_d(fi, 1)] = Real(d1y * p.i60dy);
+        q[q_d(fi, 1)] = Real(d1u(pP, b, RW) * p.i60dy);
+        const double d2x = d2u(pP, b, 1), d2y = d2u(pP, b, RW);
         if (fi == LR) {
-          q[q_d(fi, 2)] = pO[0];
-          q[Q_LAPR] = Real(d2x * p.i180dx2 + d2y * p.i180dy2 + double(pO[(1 + LR) * NT]));
+          q[q_d(fi, 2)] = pON[0];
+          q[Q_LAPR] = Real(d2x * p.i180dx2 + d2y * p.i180dy2 + double(pON[on_d2(LR) * NT]));
         } else {
-          const int zb = zs_index(fi) * RPL + PC;
-          q[q_d(fi, 2)] = pZ[zb];
+          const int zb = zn_index(fi) * RPL + PC;
+          q[q_d(fi, 2)] = pZN[zb];
           q[q_h(fi, 0)] = Real(d2x * p.i180dx2);
           q[q_h(fi, 1)] = Real(d2y * p.i180dy2);
-          q[q_h(fi, 2)] = pO[(1 + fi) * NT];
-          if (q_h(fi, 4) >= 0) q[q_h(fi, 4)] = d1u(pZ, zb, 1) * Real(p.i60dx);
-          if (q_h(fi, 5) >= 0) q[q_h(fi, 5)] = d1u(pZ, zb, RW) * Real(p.i60dy);
+          q[q_h(fi, 2)] = pON[on_d2(fi) * NT];
+          if (q_h(fi, 4) >= 0) q[q_h(fi, 4)] = d1u(pZN, zb, 1) * Real(p.i60dx);
+          if (q_h(fi, 5) >= 0) q[q_h(fi, 5)] = d1u(pZN, zb, RW) * Real(p.i60dy);
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
     // D1_x on the y-halo rows (threads 0..95)
     if (tid < 2 * NG * TX) {
-      const auto pPh = lds_base(&S.P[0][hrow * RW + hcol + 4 - NG]);
-      const auto pDh = lds_base(&S.Dx[0][hrow * DXW + hcol]);
+      const int ih = opaque(hrow * RW + hcol + 4 - NG), ihx = opaque(hrow * DXW + hcol);
 #pragma unroll
-      for (int fi = 0; fi < NF; ++fi)
-        if (dx_index(fi) >= 0) pDh[dx_index(fi) * DXH * DXW] = d1u(pPh, fi * RPL + NG, 1);
+      for (int fi = 0; fi < NF; ++fi) {
+        if (dx_index(fi) < 0) continue;
+        const double* pP = (fi <= AZ ? &sPA[0][0] : &sPN[0][0]) + ih;
+        const int b = (fi <= AZ ? fi : fi - UX) * RPL + NG;
+        (&sDx[0][0] + ihx)[dx_index(fi) * DXP] = d1u(pP, b, 1);
+      }
     }
-    __syncthreads();
+    lds_barrier();
+
+    // ---- copies into the arrays last read in 1a: the RK register of this
+    // plane and the non-A fields of the next plane
+    if (READ_DF) {
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) cp.template own<8>(dF + fi * sf + (k + NG) * sp, sDF[fi], cp.od);
+    }
+    if (k + 1 < kend) copy_plane(k + 1, false);
 
     // ---- 1b: xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
     const double ixy = p.i60dx * p.i60dy;
 #pragma unroll
     for (int fi = UX; fi < NF; ++fi)
-      if (dx_index(fi) >= 0)
-        q[q_h(fi, 3)] = Real(d1u(pD, dx_index(fi) * DXH * DXW + DC, DXW) * ixy);
+      if (dx_index(fi) >= 0) q[q_h(fi, 3)] = Real(d1u(pDx, dx_index(fi) * DXP + DC, DXW) * ixy);
 
-    // ---- 2a: magnetic part of the right-hand side (A read from LDS)
+    // ---- 2a: radiative loss and the magnetic part (A read from LDS)
     PointCtx<Real> pc;
     swamp(p, k, pc.w, pc.dw);
     pc.bottom = SOLAR && k == 0;
@@ -382,31 +450,29 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     } else {
       pc.uh[0] = pc.uh[1] = pc.ah[0] = pc.ah[1] = Real(0.0);
     }
-    const HybridSource<Real> src{q,      v64,     pP,        pZ,        pO, pD,
+    const HybridSource<Real> src{q, v64, pPA, &sZA[0][0] + ic, &sOA[0][0] + it, pDx,
                                  p.i60dx, p.i60dy, p.i180dx2, p.i180dy2, ixy};
     Real out[NF];
     MagState<Real> mag;
+    const Real rad = rhs_radiation<Real>(src, p, LdsRadTable{sRad});
     rhs_magnetic<Real>(src, pc, p, out, mag);
-    __syncthreads();
+    lds_barrier();
 
-    // ---- copies: the RK register of this plane, then the next plane
-    if (READ_DF) cp.rk_register(S, dF, sf, sp, k);
-    if (k + 1 < kend) cp.plane(S, f, dz, sf, sp, szs, k + 1);
+    // ---- copies of the A fields of the next plane
+    if (k + 1 < kend) copy_plane(k + 1, true);
 
     // ---- 2b: fluid part of the right-hand side, from registers
-    rhs_fluid<Real>(src, pc, p, mag, out);
+    rhs_fluid<Real>(src, pc, p, mag, rad, out);
 
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    copies_barrier();
 
     // ---- 3: 2N-RK3 register update in float64
-    const auto pF = lds_base(&S.DF[0][tid]);
     const unsigned ob = unsigned(oc) * 8u;   // byte offset of the own column
 #pragma unroll
     for (int fi = 0; fi < NF; ++fi) {
       const long long pl = fi * sf + (k + NG) * sp;   // uniform
       const double r = double(out[fi]);
-      double d = READ_DF ? st.alpha * pF[fi * NT] + st.dt * r : st.dt * r;
+      double d = READ_DF ? st.alpha * sDF[fi][tid] + st.dt * r : st.dt * r;
       double fn = v64[fi] + st.beta * d;
       if (SOLAR) {
         // closed boundary (u_z = 0 at both boundary planes) and the
@@ -466,17 +532,22 @@ hipError_t launch_typed(const KParams& p, int stage, const double* f, const void
                         hipStream_t s) {
   int kchunk;
   const int nchunk = zchunks(p, 2048, kchunk);
-  dim3 grid(p.nx / TX, p.ny / TY, nchunk);
+  TileMap tm{p.nx / TX, p.ny / TY, 8, 4, 0};
+  tm.pw = tm.ntx < tm.pw ? tm.ntx : tm.pw;
+  tm.ph = tm.nty < tm.ph ? tm.nty : tm.ph;
+  // XCD-aware order when the patches split evenly over the 8 XCDs
+  tm.xcd = ((tm.ntx / tm.pw) * (tm.nty / tm.ph) * nchunk) % 8 == 0;
+  dim3 grid(unsigned(tm.ntx * tm.nty * nchunk));
   const Real* dz = static_cast<const Real*>(dzv);
   if (stage == 0)
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, false, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk);
+                       uh, ah, p, st, kchunk, tm);
   else if (stage == 1)
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk);
+                       uh, ah, p, st, kchunk, tm);
   else
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, false>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk);
+                       uh, ah, p, st, kchunk, tm);
   return hipGetLastError();
 }
 
