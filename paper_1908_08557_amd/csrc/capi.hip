@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "cmhd_internal.h"
@@ -26,6 +27,11 @@ struct cmhd_ctx {
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
   void* dz = nullptr;     // z derivatives of the substage input [16][nz][ny][nx]
+  // second stream for the z-derivative pass of the pipelined substage, and
+  // the events that order it against the caller's stream (created at init)
+  hipStream_t zs = nullptr;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_z;
   std::string err;
   // adjoint workspace
   char* aws = nullptr;
@@ -34,6 +40,9 @@ struct cmhd_ctx {
   // per timed kernel (CMHD_PROF_*): event pairs recorded and not yet read
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2], ev_free;
   ~cmhd_ctx() {
+    for (auto& e : ev_z) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (zs) (void)hipStreamDestroy(zs);
     for (auto& v : ev_pending)
       for (auto& e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -244,6 +253,17 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
   c->par = q;
   c->stream = (hipStream_t)stream;
   fill_kparams(c, lnrho0_z);
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    c->ev_z.assign(size_t(plan_chunks(c->kp).nchunk), nullptr);
+    for (auto& ev : c->ev_z)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete c;
+      return CMHD_EDEVICE;
+    }
+  }
   *out = c;
   return CMHD_OK;
 }
@@ -359,17 +379,52 @@ hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which)
 }
 
 // one substage from src to dst (ghosts of src already filled): z-derivative
-// pass, fused stencil/RHS/RK kernel, nudged ghost rows
+// pass, fused stencil/RHS/RK kernel, nudged ghost rows.  On large grids the
+// substage is pipelined over z chunks: the z-derivative pass runs chunk by
+// chunk on the second stream (forked from the caller's stream) and the fused
+// kernel of chunk c waits only for the z derivatives of chunk c, so that the
+// streaming pass shares the CUs with the latency-bound fused kernel.  All work
+// is joined back into the caller's stream before the substage ends.
 hipError_t substage(cmhd_ctx* c, int s, const double* src, double* dst, double* dF,
                     const StageArgs& a) {
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  hipError_t e = ev_begin(c, ev);
-  if (e == hipSuccess) e = launch_zderiv(c->kp, c->grid.prec, src, c->dz, c->stream);
-  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_ZDERIV);
-  if (e == hipSuccess) e = ev_begin(c, ev);
-  if (e == hipSuccess)
-    e = launch_rhs_rk(c->kp, c->grid.prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, c->stream);
-  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_SUBSTAGE);
+  const ChunkPlan cp = plan_chunks(c->kp);
+  const int prec = c->grid.prec;
+  std::pair<hipEvent_t, hipEvent_t> ev_all, ev_zd;
+  hipError_t e = ev_begin(c, ev_all);
+  if (!cp.pipelined) {
+    if (e == hipSuccess) e = ev_begin(c, ev_zd);
+    if (e == hipSuccess) e = launch_zderiv(c->kp, prec, src, c->dz, 0, c->kp.nz, c->stream);
+    if (e == hipSuccess) e = ev_end(c, ev_zd, CMHD_PROF_ZDERIV);
+    if (e == hipSuccess)
+      e = launch_rhs_rk(c->kp, prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, cp, 0, cp.nchunk,
+                        c->stream);
+  } else {
+    if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->zs, c->ev_fork, 0);
+    if (e == hipSuccess && c->profiling) {
+      // z-pass timing on its own stream
+      std::swap(c->stream, c->zs);
+      e = ev_begin(c, ev_zd);
+      std::swap(c->stream, c->zs);
+    }
+    for (int ch = 0; ch < cp.nchunk && e == hipSuccess; ++ch) {
+      const int k0 = ch * cp.kchunk, k1 = std::min(c->kp.nz, k0 + cp.kchunk);
+      e = launch_zderiv(c->kp, prec, src, c->dz, k0, k1, c->zs);
+      if (e == hipSuccess) e = hipEventRecord(c->ev_z[ch], c->zs);
+    }
+    if (e == hipSuccess && c->profiling) {
+      std::swap(c->stream, c->zs);
+      e = ev_end(c, ev_zd, CMHD_PROF_ZDERIV);
+      std::swap(c->stream, c->zs);
+    }
+    for (int ch = 0; ch < cp.nchunk && e == hipSuccess; ++ch) {
+      e = hipStreamWaitEvent(c->stream, c->ev_z[ch], 0);
+      if (e == hipSuccess)
+        e = launch_rhs_rk(c->kp, prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, cp, ch, 1,
+                          c->stream);
+    }
+  }
+  if (e == hipSuccess) e = ev_end(c, ev_all, CMHD_PROF_SUBSTAGE);
   if (e == hipSuccess && c->kp.solar)
     e = launch_ghost_rows(c->kp, src, dst, dF, c->uh, a, s > 0, s < 2, c->stream);
   return e;

@@ -57,10 +57,22 @@ constexpr double RK_C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
 // bytes of the z-derivative buffer (16 slots of nz planes, in the precision
 // of the right-hand side)
 size_t zderiv_bytes(const KParams& p, int prec);
-hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, hipStream_t s);
+// How a substage is cut into z chunks: the fused kernel marches kchunk planes
+// per block.  pipelined: one fused launch per chunk, the z-derivative pass of
+// chunk c overlapping the fused kernel of chunk c-1 on a second stream.
+struct ChunkPlan {
+  int kchunk, nchunk;
+  bool pipelined;
+};
+ChunkPlan plan_chunks(const KParams& p);
+// z derivatives of planes [k0, k1)
+hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, int k0, int k1,
+                         hipStream_t s);
+// fused substage kernel over the chunks [chunk0, chunk0 + nchunks) of the plan
 hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, const void* dz,
                          double* fo, double* dF, const double* uh, const double* ah,
-                         StageArgs st, hipStream_t s);
+                         StageArgs st, const ChunkPlan& cp, int chunk0, int nchunks,
+                         hipStream_t s);
 hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,
                              const double* uh, StageArgs st, int read_dF, int write_dF,
                              hipStream_t s);

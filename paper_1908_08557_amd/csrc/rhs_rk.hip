@@ -270,12 +270,12 @@ __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double
 template <typename Real>
 __global__ __launch_bounds__(256) void k_zderiv(const double* __restrict__ f,
                                                 Real* __restrict__ dz, const KParams p,
-                                                int kchunk) {
+                                                int kfirst, int klast, int kchunk) {
   const long long sp = p.splane;
   const long long col = blockIdx.x * 256LL + threadIdx.x;
   const int fi = blockIdx.y;
-  const int k0 = blockIdx.z * kchunk;
-  const int k1 = min(k0 + kchunk, p.nz);
+  const int k0 = kfirst + blockIdx.z * kchunk;
+  const int k1 = min(k0 + kchunk, klast);
   const long long szs = (long long)p.nz * sp;
   const double* a = f + fi * p.sfield + col;   // array plane j at a[j * sp]
   Real* o1 = dz + fi * szs + col;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                                double* __restrict__ dF,
                                                const double* __restrict__ uh,
                                                const double* __restrict__ ah, const KParams p,
-                                               const StageArgs st, int kchunk,
+                                               const StageArgs st, int kchunk, int chunk0,
                                                const TileMap tm) {
   __shared__ __align__(16) double sPA[NA][RPL];   // values of A, haloed
   __shared__ __align__(16) double sPN[NN][RPL];   // values of u, ln rho, ln T, haloed
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
   const int hrow = tid < 3 * TX ? tid / TX : TY + NG + (tid - 3 * TX) / TX;
   const int hcol = tid % TX;
 
-  const int kbeg = bz * kchunk;
+  const int kbeg = (chunk0 + bz) * kchunk;
   const int kend = min(kbeg + kchunk, p.nz);
 
   if (tid < CMHD_MAX_RAD) {
@@ -509,45 +509,37 @@ __global__ void k_ghost_rows(const double* __restrict__ f, double* __restrict__ 
   }
 }
 
-int zchunks(const KParams& p, int target_blocks, int& kchunk) {
-  const int tiles = (p.nx / TX) * (p.ny / TY);
-  int nchunk = (target_blocks + tiles - 1) / tiles;
-  if (nchunk > p.nz) nchunk = p.nz;
-  kchunk = (p.nz + nchunk - 1) / nchunk;
-  return (p.nz + kchunk - 1) / kchunk;
-}
-
 template <typename Real>
-hipError_t launch_zderiv_typed(const KParams& p, const double* f, void* dz, hipStream_t s) {
+hipError_t launch_zderiv_typed(const KParams& p, const double* f, void* dz, int k0, int k1,
+                               hipStream_t s) {
   const int kchunk = 32;
-  const int nchunk = (p.nz + kchunk - 1) / kchunk;
+  const int nchunk = (k1 - k0 + kchunk - 1) / kchunk;
   dim3 grid(unsigned(p.splane / 256), NF, nchunk);
-  hipLaunchKernelGGL(k_zderiv<Real>, grid, dim3(256), 0, s, f, static_cast<Real*>(dz), p, kchunk);
+  hipLaunchKernelGGL(k_zderiv<Real>, grid, dim3(256), 0, s, f, static_cast<Real*>(dz), p, k0, k1,
+                     kchunk);
   return hipGetLastError();
 }
 
 template <typename Real, bool SOLAR>
 hipError_t launch_typed(const KParams& p, int stage, const double* f, const void* dzv,
                         double* fo, double* dF, const double* uh, const double* ah, StageArgs st,
-                        hipStream_t s) {
-  int kchunk;
-  const int nchunk = zchunks(p, 2048, kchunk);
+                        const ChunkPlan& cp, int chunk0, int nchunks, hipStream_t s) {
   TileMap tm{p.nx / TX, p.ny / TY, 8, 4, 0};
   tm.pw = tm.ntx < tm.pw ? tm.ntx : tm.pw;
   tm.ph = tm.nty < tm.ph ? tm.nty : tm.ph;
   // XCD-aware order when the patches split evenly over the 8 XCDs
-  tm.xcd = ((tm.ntx / tm.pw) * (tm.nty / tm.ph) * nchunk) % 8 == 0;
-  dim3 grid(unsigned(tm.ntx * tm.nty * nchunk));
+  tm.xcd = ((tm.ntx / tm.pw) * (tm.nty / tm.ph) * nchunks) % 8 == 0;
+  dim3 grid(unsigned(tm.ntx * tm.nty * nchunks));
   const Real* dz = static_cast<const Real*>(dzv);
   if (stage == 0)
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, false, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk, tm);
+                       uh, ah, p, st, cp.kchunk, chunk0, tm);
   else if (stage == 1)
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk, tm);
+                       uh, ah, p, st, cp.kchunk, chunk0, tm);
   else
     hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, false>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, kchunk, tm);
+                       uh, ah, p, st, cp.kchunk, chunk0, tm);
   return hipGetLastError();
 }
 
@@ -558,19 +550,44 @@ size_t zderiv_bytes(const KParams& p, int prec) {
   return size_t(NZSLOT) * size_t(p.nz) * size_t(p.splane) * el;
 }
 
-hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, hipStream_t s) {
-  return prec == CMHD_FP32_SPLIT ? launch_zderiv_typed<float>(p, f, dz, s)
-                                 : launch_zderiv_typed<double>(p, f, dz, s);
+ChunkPlan plan_chunks(const KParams& p) {
+  ChunkPlan c;
+  const int tiles = (p.nx / TX) * (p.ny / TY);
+  if (tiles >= 256 && p.nz >= 32) {
+    // pipelined: z chunks of a quarter of the box (at least 16 planes), one
+    // fused launch per chunk of all tiles
+    c.kchunk = (p.nz + 3) / 4;
+    c.kchunk = c.kchunk < 16 ? 16 : c.kchunk;
+    c.nchunk = (p.nz + c.kchunk - 1) / c.kchunk;
+    c.pipelined = true;
+  } else {
+    // one launch of about 2048 blocks
+    int nchunk = (2048 + tiles - 1) / tiles;
+    if (nchunk > p.nz) nchunk = p.nz;
+    c.kchunk = (p.nz + nchunk - 1) / nchunk;
+    c.nchunk = (p.nz + c.kchunk - 1) / c.kchunk;
+    c.pipelined = false;
+  }
+  return c;
+}
+
+hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, int k0, int k1,
+                         hipStream_t s) {
+  return prec == CMHD_FP32_SPLIT ? launch_zderiv_typed<float>(p, f, dz, k0, k1, s)
+                                 : launch_zderiv_typed<double>(p, f, dz, k0, k1, s);
 }
 
 hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, const void* dz,
                          double* fo, double* dF, const double* uh, const double* ah,
-                         StageArgs st, hipStream_t s) {
+                         StageArgs st, const ChunkPlan& cp, int chunk0, int nchunks,
+                         hipStream_t s) {
   if (prec == CMHD_FP32_SPLIT)
-    return p.solar ? launch_typed<float, true>(p, stage, f, dz, fo, dF, uh, ah, st, s)
-                   : launch_typed<float, false>(p, stage, f, dz, fo, dF, uh, ah, st, s);
-  return p.solar ? launch_typed<double, true>(p, stage, f, dz, fo, dF, uh, ah, st, s)
-                 : launch_typed<double, false>(p, stage, f, dz, fo, dF, uh, ah, st, s);
+    return p.solar
+               ? launch_typed<float, true>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s)
+               : launch_typed<float, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
+  return p.solar
+             ? launch_typed<double, true>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s)
+             : launch_typed<double, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
 }
 
 hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,

@@ -83,6 +83,35 @@ def test_strat64_one_step():
     assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12, "strat64 1 step")
 
 
+_PIPELINED = {}   # oracle result shared by the two precisions
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
+def test_pipelined_substage(precision):
+    # 256 x 256 x 32 (256 tiles, two z chunks): the substage runs its
+    # z-derivative pass on a second stream, chunk by chunk, overlapping the
+    # fused kernel.  FP64 against the oracle after two steps; the FP32-split
+    # form against the same oracle at its own tolerance.
+    import torch
+    from paper_1908_08557_amd import cmhd
+    w = W.small_stratified(256, 256, 32, Lxy=80.0, z1=20.0, nbip=4)
+    print(f"[case] pipelined substage 256x256x32 {precision}", flush=True)
+    if "ref" not in _PIPELINED:
+        _PIPELINED["dt"] = oracle_dt(w)
+        _PIPELINED["ref"] = oracle_run(w, 2, _PIPELINED["dt"])
+    dt = _PIPELINED["dt"]
+    s = cmhd.solver_for(w, precision)
+    st = s.new_state(w.state)
+    t = 0.0
+    for _ in range(2):
+        t, _ = s.rk3_step(st, t, dt)
+    got = st.cpu().numpy()
+    ref = _PIPELINED["ref"]
+    assert_parity(got, ref, True, 1e-12 if precision == "fp64" else 2e-6,
+                  f"pipelined 256x256x32 {precision}")
+
+
 @pytest.mark.timeout(900)
 def test_strat64_hundred_steps():
     w = W.strat64()
