@@ -40,6 +40,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per substage from the committed rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE scaled by the copy calibration), if they were taken on the
+    kernel sources as they are now; otherwise None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "substage_strat512_fp64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def run_gpu(w, precision, steps, warmup, drivers):
     import torch
 
@@ -184,6 +199,12 @@ def main():
                              "roofline_frac": s["frac"],
                              "substage_ms": s["substage_ms"],
                              "k_zderiv_ms": s["zderiv_ms_per_launch"]}
+    tr = measured_traffic() if (w.name == "strat512" and main_prec == "fp64") else None
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["hbm_bytes_per_substage"]
+        out["roofline"]["traffic_GBs"] = tr["hbm_bytes_per_substage"] / (r["substage_ms"] * 1e-3) / 1e9
+        out["roofline"]["traffic_source"] = tr["profile"]
+        out["roofline"]["valu_busy_pct"] = tr["valu_busy_pct_fused"]
     out["finite"] = all(v["finite"] for v in res.values())
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample)")
