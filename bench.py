@@ -104,7 +104,8 @@ def run_gpu(w, precision, steps, warmup, drivers):
 
 def cpu_baseline():
     """The oracle as it stands, on a bounded sample: a 128 x 128 x 64 box with
-    the 512^2 x 256 box's grid spacing and physics, two RK3 steps."""
+    the 512^2 x 256 box's grid spacing and physics, eight RK3 steps (about
+    10 s of single-thread numpy work)."""
     from oracle import mhd as O
     from paper_1908_08557_amd import workloads as W
     nx, nz = 128, 64
@@ -114,7 +115,7 @@ def cpu_baseline():
     O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
     dt = O.cfl_dt(F, w.grid, w.params)
     drv = dict(uh=w.uh_target, ah=w.ah_target)
-    nsteps = 2
+    nsteps = 8
     t0 = time.perf_counter()
     O.run(F, 0.0, dt, nsteps, w.grid, w.params, w.lnrho0_z, drv)
     el = time.perf_counter() - t0
