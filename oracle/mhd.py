@@ -302,6 +302,53 @@ def q_rad(rho, lnT, par):
             * rad_cut(lnT, par["T_rad_lo"], par["T_rad_hi"]))
 
 
+def sine_cutoff(x, start, width):
+    """1 for x <= start, 0 for x >= start + width, a sine transition between
+    (1/2 [1 - sin(pi (x - start - width/2) / width)]).  Complex-safe: the
+    branch is taken on the real part."""
+    xr = np.real(x)
+    mid = 0.5 * (1.0 - np.sin(np.pi * (x - start - 0.5 * width) / width))
+    return np.where(xr <= start, 1.0, np.where(xr >= start + width, 0.0, mid))
+
+
+def newton_cooling(lr, lT, z, k_index, par):
+    """Chromospheric Newtonian cooling (Sect. 3.1, eqs. 9-10): contribution to
+    d ln T/dt at zones with ln rho = lr, ln T = lT, height z (array index of
+    the plane k_index, broadcast like lr).
+
+    Target (eq. 9): T* = sqrt(T0(z) T'(rho)), T'(rho) = T0(z') at the height
+    z' where the initial density equals the actual one, rho0(z') = rho.  The
+    initial profiles are tabulated at the grid heights z_k, k = -3 .. nz+2
+    (par['nc_lnrho0_z'], par['nc_lnT0_z']); z' is found by linear
+    interpolation in ln rho0 between the bracketing nodes, clamped to the end
+    values outside the table.
+    Term (reading of the garbled eq. 10): d ln T/dt = -tau_t c_rho c_z (1 - T*/T),
+    i.e. dT/dt = -tau_t c_rho c_z (T - T*), an exponential decay of T toward
+    T* at the inverse time tau_t.
+    Cutoffs: c_rho = 1 while ln rho is within nc_lnrho_magn - nc_lnrho_width
+    natural-log orders of the photospheric density rho0(0), a sine down to 0
+    over the last nc_lnrho_width orders; c_z = 1 below nc_z_max -
+    nc_z_width, a sine down to 0 at nc_z_max."""
+    tau = par.get("nc_tau", 0.0)
+    if tau == 0.0:
+        return 0.0 * lT
+    x = np.asarray(par["nc_lnrho0_z"], dtype=np.float64)   # decreasing with z
+    y = np.asarray(par["nc_lnT0_z"], dtype=np.float64)
+    n = len(x)
+    # bracketing segment [i, i+1] with x[i] >= lr > x[i+1], on the real part
+    lrr = np.real(lr)
+    i = np.sum(x[None, :] >= np.reshape(lrr, (-1, 1)), axis=1).reshape(np.shape(lrr)) - 1
+    i = np.clip(i, 0, n - 2)
+    w = (x[i] - lr) / (x[i] - x[i + 1])
+    lTp = y[i] + w * (y[i + 1] - y[i])
+    lTp = np.where(lrr >= x[0], y[0], np.where(lrr <= x[-1], y[-1], lTp))
+    lTstar = 0.5 * (y[k_index] + lTp)
+    c_rho = sine_cutoff(x[NG] - lr, par["nc_lnrho_magn"] - par["nc_lnrho_width"],
+                        par["nc_lnrho_width"])
+    c_z = sine_cutoff(z, par["nc_z_max"] - par["nc_z_width"], par["nc_z_width"])
+    return -tau * c_rho * c_z * (1.0 - np.exp(lTstar - lT))
+
+
 # ---------------------------------------------------------------------------
 # Steps 2-3: right-hand side
 # ---------------------------------------------------------------------------
@@ -430,6 +477,10 @@ def rhs(F, t, grid, par, drv):
     lapT = HT[0][0] + HT[1][1] + HT[2][2]
     RT = (-udT - (gam - 1.0) * divu + (ohm + vheat + qcond - qrad) / (rho * cv * T)
           + par["chi_s"] * w * lapT)
+    if par.get("nc_tau", 0.0) != 0.0:
+        kk = np.arange(NG, NG + nz)[:, None, None] + np.zeros(lT.shape, dtype=int)
+        zz = zk(grid)[kk]
+        RT = RT + newton_cooling(lr, lT, zz, kk, par)
 
     R = np.stack(RA + Ru + [Rr, RT])
     Rgh = None
@@ -495,7 +546,7 @@ def run(F, t, dt, nsteps, grid, par, lnrho0_z, drv=None):
 
 def cfl_dt(F, grid, par):
     """dt = min(c_adv d/max(|u| + c_f), c_diff d^2/max D_eff,
-    c_adv min(rho c_v T / Q_rad), c_nudge/max(tau_u, tau_A)) over the
+    c_adv min(rho c_v T / Q_rad), c_nudge/max(tau_u, tau_A, tau_t)) over the
     interior, from a ghost-filled state F (reading: the paper gives only the
     Courant number 0.4 and the Spitzer limitation)."""
     h = spacings(grid)
@@ -538,6 +589,7 @@ def cfl_dt(F, grid, par):
         pos = qr > 0
         dt = min(dt, par["c_adv"] * np.min(rho[pos] * cv * T[pos] / qr[pos]))
     tau = max(par["tau_u"], par["tau_A"]) if grid["zbc"] == "solar" else 0.0
+    tau = max(tau, par.get("nc_tau", 0.0))
     if tau > 0:
         dt = min(dt, par["c_nudge"] / tau)
     return float(dt)

@@ -109,6 +109,8 @@ def base_params():
                 tau_u=0.0, tau_A=0.0, t_ramp=0.0, f_bot=0.2,
                 rad_lnT=np.zeros(0), rad_lnL=np.zeros(0),
                 T_rad_lo=1e4, T_rad_hi=2e4,
+                nc_tau=0.0, nc_lnrho_magn=8.0, nc_lnrho_width=2.0, nc_z_max=3.0,
+                nc_z_width=0.3,
                 c_adv=0.4, c_diff=0.12, c_nudge=1.0)
 
 
@@ -275,6 +277,17 @@ def periodic_box(n=16, seed_A=0, seed_u=1, amp_A=1e-2, amp_u=1e-3, eta=1e-3, nu=
     state[3:6] = modes(seed_u, amp_u)
     return Workload(name=f"periodic{n}", grid=grid, params=p,
                     lnrho0_z=np.zeros(n + 6), lnT0_z=np.zeros(n + 6), state=state)
+
+
+def enable_newton_cooling(w: "Workload", tau=0.5 * U_T):
+    """Switch on the chromospheric Newtonian cooling (Sect. 3.1; tau_t =
+    0.5 s^-1, cutoffs 8 natural-log orders below the photospheric density with
+    a sine over the last 2, and 3 Mm with a sine over the top 0.3 Mm) with the
+    workload's initial profiles as its reference stratification."""
+    w.params.update(nc_tau=tau, nc_lnrho_magn=8.0, nc_lnrho_width=2.0, nc_z_max=3.0,
+                    nc_z_width=0.3, nc_lnrho0_z=np.array(w.lnrho0_z),
+                    nc_lnT0_z=np.array(w.lnT0_z))
+    return w
 
 
 def stratified_box(nx, ny, nz, Lxy, z1, nbip, seed_bip, seed_u, name, t_ramp=None):
