@@ -59,6 +59,7 @@ typedef enum { CMHD_FP64 = 0, CMHD_FP32_SPLIT = 1 } cmhd_precision;
 typedef enum { CMHD_ZBC_PERIODIC = 0, CMHD_ZBC_SOLAR = 1 } cmhd_zbc;
 
 #define CMHD_MAX_RAD 16
+#define CMHD_MAX_NC_TABLE 1024   /* nz + 6 <= this when the Newtonian cooling is on */
 
 typedef struct cmhd_ctx cmhd_ctx;
 
@@ -100,6 +101,18 @@ typedef struct {
  *                    constant outside; n_rad = 0 switches it off
  *  T_rad_lo, T_rad_hi smoothstep in ln T that switches the loss on
  *  c_adv, c_diff, c_nudge   Courant factors of cmhd_cfl_dt
+ *  nc_tau            inverse time of the chromospheric Newtonian cooling
+ *                    (Sect. 3.1, eqs. 9-10): d ln T/dt gains
+ *                    -nc_tau c_rho c_z (1 - Ts / T) with the target
+ *                    Ts = sqrt(T0(z) T'(rho)), T'(rho) = T0(z') where
+ *                    rho0(z') = rho (linear in ln rho0 between the nodes of
+ *                    the initial profiles given to cmhd_init_grid, clamped
+ *                    outside); 0 switches it off
+ *  nc_lnrho_magn, nc_lnrho_width   c_rho = 1 while ln rho is within
+ *                    magn - width natural-log orders of the photospheric
+ *                    ln rho0(z0), a sine down to 0 at magn orders
+ *  nc_z_max, nc_z_width   c_z = 1 below nc_z_max - nc_z_width, a sine down
+ *                    to 0 at nc_z_max
  * Periodic z ignores the swamp, nudging and boundary parameters. */
 typedef struct {
   double gamma, R, mu0, eta, nu, D_rho, kappa0, g_z;
@@ -111,16 +124,22 @@ typedef struct {
   double rad_lnT[CMHD_MAX_RAD], rad_lnL[CMHD_MAX_RAD];
   double T_rad_lo, T_rad_hi;
   double c_adv, c_diff, c_nudge;
+  double nc_tau, nc_lnrho_magn, nc_lnrho_width, nc_z_max, nc_z_width;
 } cmhd_params;
 
 /* Create a context.  lnrho0_z: host array of nz+6 doubles, the initial
  * ln rho profile at z_k, k = -3..nz+2; its three lowest entries are the
  * density imposed below the photosphere ('fg', Sect. 2.5) and entry 3 the
- * photospheric value held fixed.  It is copied.  stream: a hipStream_t (NULL
- * = the null stream).  *out receives the context.  EINVAL on bad sizes or
- * parameters, EDEVICE when no gfx950 device is current. */
+ * photospheric value held fixed.  lnT0_z: host array of nz+6 doubles, the
+ * initial ln T profile at the same heights; only the Newtonian cooling reads
+ * it (then lnrho0_z must decrease strictly with height, the reference
+ * stratification of Sect. 3.1) and it may be NULL when params->nc_tau == 0.
+ * Both are copied.  stream: a hipStream_t (NULL = the null stream).  *out
+ * receives the context.  EINVAL on bad sizes or parameters, EDEVICE when no
+ * gfx950 device is current. */
 cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
-                           const double* lnrho0_z, void* stream, cmhd_ctx** out);
+                           const double* lnrho0_z, const double* lnT0_z, void* stream,
+                           cmhd_ctx** out);
 
 /* Number of doubles of one state buffer: 8*(nz+6)*ny*nx. */
 size_t cmhd_state_elems(const cmhd_ctx* ctx);

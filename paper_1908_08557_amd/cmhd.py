@@ -38,7 +38,9 @@ class CmhdParams(ctypes.Structure):
         ("eta_s", "chi_s", "chi_rho", "z_s", "z_t", "tau_u", "tau_A", "t_ramp", "f_bot")] + [
         ("n_rad", ctypes.c_int), ("rad_lnT", ctypes.c_double * MAX_RAD),
         ("rad_lnL", ctypes.c_double * MAX_RAD)] + [
-        (n, ctypes.c_double) for n in ("T_rad_lo", "T_rad_hi", "c_adv", "c_diff", "c_nudge")]
+        (n, ctypes.c_double) for n in ("T_rad_lo", "T_rad_hi", "c_adv", "c_diff", "c_nudge")] + [
+        (n, ctypes.c_double) for n in
+        ("nc_tau", "nc_lnrho_magn", "nc_lnrho_width", "nc_z_max", "nc_z_width")]
 
 
 class CmhdError(RuntimeError):
@@ -62,7 +64,7 @@ def load():
     P, D, I, U, S = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_uint, ctypes.c_size_t
     sig = {
         "cmhd_init_grid": (I, [ctypes.POINTER(CmhdGrid), ctypes.POINTER(CmhdParams),
-                               ctypes.POINTER(D), P, ctypes.POINTER(P)]),
+                               ctypes.POINTER(D), ctypes.POINTER(D), P, ctypes.POINTER(P)]),
         "cmhd_state_elems": (S, [P]),
         "cmhd_workspace_bytes": (S, [P]),
         "cmhd_bind_workspace": (I, [P, P, S]),
@@ -118,6 +120,9 @@ def make_params(par: dict) -> CmhdParams:
                  "eta_s", "chi_s", "chi_rho", "z_s", "z_t", "tau_u", "tau_A", "t_ramp", "f_bot",
                  "T_rad_lo", "T_rad_hi", "c_adv", "c_diff", "c_nudge"):
         setattr(p, name, float(par[name]))
+    for name, default in (("nc_tau", 0.0), ("nc_lnrho_magn", 8.0), ("nc_lnrho_width", 2.0),
+                          ("nc_z_max", 3.0), ("nc_z_width", 0.3)):
+        setattr(p, name, float(par.get(name, default)))
     for i in range(3):
         p.Bext[i] = float(par["Bext"][i])
     lnT = np.asarray(par["rad_lnT"], dtype=np.float64)
@@ -139,7 +144,7 @@ class Solver:
     """One library context: grid, parameters, bound workspace."""
 
     def __init__(self, grid: dict, params: dict, lnrho0_z, precision: str = "fp64",
-                 device: str = "cuda"):
+                 device: str = "cuda", lnT0_z=None):
         self.lib = load()
         self.grid = dict(grid)
         self.params = dict(params)
@@ -149,11 +154,15 @@ class Solver:
         self._p = make_params(params)
         lr = np.ascontiguousarray(np.asarray(lnrho0_z, dtype=np.float64))
         self._lr = lr
+        if lnT0_z is None and "nc_lnT0_z" in params:
+            lnT0_z = params["nc_lnT0_z"]
+        lt = None if lnT0_z is None else np.ascontiguousarray(np.asarray(lnT0_z, np.float64))
+        self._lt = lt
+        dptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        rc = self.lib.cmhd_init_grid(ctypes.byref(self._g), ctypes.byref(self._p),
-                                     lr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                     ctypes.c_void_p(stream), ctypes.byref(ctx))
+        rc = self.lib.cmhd_init_grid(ctypes.byref(self._g), ctypes.byref(self._p), dptr(lr),
+                                     dptr(lt), ctypes.c_void_p(stream), ctypes.byref(ctx))
         if rc != CMHD_OK:
             raise CmhdError(rc, "cmhd_init_grid failed (see stderr)")
         self.ctx = ctx
@@ -322,7 +331,8 @@ class Solver:
 
 def solver_for(workload, precision="fp64", device="cuda"):
     """Solver for a workloads.Workload, with its driver already set."""
-    s = Solver(workload.grid, workload.params, workload.lnrho0_z, precision, device)
+    s = Solver(workload.grid, workload.params, workload.lnrho0_z, precision, device,
+               lnT0_z=workload.lnT0_z)
     if workload.grid["zbc"] == "solar" and workload.uh_target is not None:
         s.set_driver(workload.uh_target, ah=workload.ah_target)
     return s

@@ -151,6 +151,8 @@ __device__ PointCtx<Dual> point_ctx(const KParams& p, int k, long long col, cons
   pc.bottom = p.solar && k == 0;
   pc.top = p.solar && k == p.nz - 1;
   pc.ramp = ramp;
+  pc.nc_cz = nc_height_cut(p, k);
+  pc.nc_lnT0 = p.nc_tau != 0.0 ? p.nc_tab[p.nc_n + k + NG] : 0.0;
   if (pc.bottom) {
     pc.uh[0] = Dual(uh[col], duh ? duh[col] : 0.0);
     pc.uh[1] = Dual(uh[p.splane + col], duh ? duh[p.splane + col] : 0.0);

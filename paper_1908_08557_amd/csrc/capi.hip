@@ -27,6 +27,8 @@ struct cmhd_ctx {
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
   void* dz = nullptr;     // z derivatives of the substage input [16][nz][ny][nx]
+  std::vector<double> nc_host;   // initial [ln rho0 | ln T0] profiles (Newtonian cooling)
+  double* nc_dev = nullptr;      // their device copy in the workspace
   // second stream for the z-derivative pass of the pipelined substage, and
   // the events that order it against the caller's stream (created at init)
   hipStream_t zs = nullptr;
@@ -69,7 +71,7 @@ size_t state_elems(const cmhd_grid& g) {
   return size_t(NF) * size_t(g.nz + 2 * NG) * size_t(g.ny) * size_t(g.nx);
 }
 
-size_t ws_layout(const cmhd_ctx* c, size_t off[8]) {
+size_t ws_layout(const cmhd_ctx* c, size_t off[16]) {
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
   const size_t sb = align256(state_elems(c->grid) * sizeof(double));
   size_t o = 0;
@@ -81,6 +83,7 @@ size_t ws_layout(const cmhd_ctx* c, size_t off[8]) {
   off[5] = o; o += align256(FFT_PLANES * plane * sizeof(double2));  // fft
   off[6] = o; o += 256;                                          // reductions
   off[7] = o; o += align256(zderiv_bytes(c->kp, c->grid.prec));  // z derivatives
+  off[8] = o; o += align256(2 * size_t(c->kp.nc_n) * sizeof(double));   // ln rho0, ln T0
   return o;
 }
 
@@ -147,6 +150,14 @@ void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
   p.c_adv = q.c_adv;
   p.c_diff = q.c_diff;
   p.c_nudge = q.c_nudge;
+  p.nc_tau = q.nc_tau;
+  p.nc_dlr0 = q.nc_lnrho_magn - q.nc_lnrho_width;
+  p.nc_dlrw = q.nc_lnrho_width;
+  p.nc_z0 = q.nc_z_max - q.nc_z_width;
+  p.nc_zw = q.nc_z_width;
+  p.nc_lnrho_phot = lnrho0_z ? lnrho0_z[NG] : 0.0;
+  p.nc_n = g.nz + 2 * NG;
+  p.nc_tab = nullptr;   // set when the workspace is bound
 }
 
 double ramp(const cmhd_ctx* c, double t) {
@@ -187,8 +198,9 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
   double dt = p.c_adv * delta / m[0];
   if (m[1] > 0.0) dt = std::fmin(dt, p.c_diff * delta * delta / m[1]);
   if (m[2] > 0.0) dt = std::fmin(dt, p.c_adv / m[2]);
-  const double tau = std::fmax(p.tau_u, p.tau_A);
-  if (p.solar && tau > 0.0) dt = std::fmin(dt, p.c_nudge / tau);
+  double tau = p.solar ? std::fmax(p.tau_u, p.tau_A) : 0.0;
+  tau = std::fmax(tau, p.nc_tau);
+  if (tau > 0.0) dt = std::fmin(dt, p.c_nudge / tau);
   if (!(dt > 0.0) || !std::isfinite(dt) || std::isnan(m[0]) || std::isnan(m[1]) ||
       std::isnan(m[2]))
     return fail(c, CMHD_ENONFINITE, "time step is not finite (state holds NaN/Inf?)");
@@ -201,7 +213,8 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
 extern "C" {
 
 cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
-                           const double* lnrho0_z, void* stream, cmhd_ctx** out) {
+                           const double* lnrho0_z, const double* lnT0_z, void* stream,
+                           cmhd_ctx** out) {
   if (!out) return CMHD_EINVAL;
   *out = nullptr;
   if (!grid || !params) return CMHD_EINVAL;
@@ -231,8 +244,20 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
     why = "z_t > z_s is required";
   else if (solar && !lnrho0_z)
     why = "solar mode needs the ln rho0(z) profile";
+  else if (!(q.nc_tau >= 0.0))
+    why = "nc_tau must be non-negative";
+  else if (q.nc_tau > 0.0 && (!lnrho0_z || !lnT0_z))
+    why = "the Newtonian cooling needs the ln rho0(z) and ln T0(z) profiles";
+  else if (q.nc_tau > 0.0 && g.nz + 2 * NG > CMHD_MAX_NC_TABLE)
+    why = "the Newtonian cooling supports nz + 6 <= CMHD_MAX_NC_TABLE";
+  else if (q.nc_tau > 0.0 && !(q.nc_lnrho_width > 0.0 && q.nc_z_width > 0.0 &&
+                               q.nc_lnrho_magn >= q.nc_lnrho_width))
+    why = "Newtonian cooling cutoffs: widths > 0 and nc_lnrho_magn >= nc_lnrho_width";
   for (int i = 0; why.empty() && i + 1 < q.n_rad; ++i)
     if (!(q.rad_lnT[i + 1] > q.rad_lnT[i])) why = "rad_lnT must increase";
+  for (int i = 0; why.empty() && q.nc_tau > 0.0 && i + 1 < g.nz + 2 * NG; ++i)
+    if (!(lnrho0_z[i + 1] < lnrho0_z[i]))
+      why = "the Newtonian cooling needs ln rho0(z) to decrease strictly with height";
   if (!why.empty()) {
     std::fprintf(stderr, "cmhd_init_grid: %s\n", why.c_str());
     return CMHD_EINVAL;
@@ -254,6 +279,14 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
   c->stream = (hipStream_t)stream;
   fill_kparams(c, lnrho0_z);
   {
+    const int n = g.nz + 2 * NG;
+    c->nc_host.assign(2 * size_t(n), 0.0);
+    for (int i = 0; i < n; ++i) {
+      c->nc_host[i] = lnrho0_z ? lnrho0_z[i] : 0.0;
+      c->nc_host[n + i] = lnT0_z ? lnT0_z[i] : 0.0;
+    }
+  }
+  {
     hipError_t e = hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     c->ev_z.assign(size_t(plan_chunks(c->kp).nchunk), nullptr);
@@ -272,13 +305,13 @@ size_t cmhd_state_elems(const cmhd_ctx* c) { return c ? state_elems(c->grid) : 0
 
 size_t cmhd_workspace_bytes(const cmhd_ctx* c) {
   if (!c) return 0;
-  size_t off[8];
+  size_t off[16];
   return ws_layout(c, off);
 }
 
 cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   if (!c) return CMHD_EINVAL;
-  size_t off[8];
+  size_t off[16];
   const size_t need = ws_layout(c, off);
   if (!dev_ptr) return fail(c, CMHD_EINVAL, "workspace pointer is NULL");
   if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0)
@@ -296,10 +329,15 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->fft = reinterpret_cast<double2*>(c->ws + off[5]);
   c->red = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
   c->dz = c->ws + off[7];
+  c->nc_dev = reinterpret_cast<double*>(c->ws + off[8]);
+  c->kp.nc_tab = c->nc_dev;
   // driver targets start at zero; the stage buffers are fully written before use
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
   hipError_t e = hipMemsetAsync(c->uh, 0, 2 * plane * sizeof(double), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ah, 0, 2 * plane * sizeof(double), c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->nc_dev, c->nc_host.data(), c->nc_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
   return hip_check(c, e, "workspace clear");
 }
 

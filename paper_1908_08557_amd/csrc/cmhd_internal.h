@@ -41,6 +41,13 @@ struct KParams {
   double lnrho0_bot[4];   // ln rho0 at k = -3, -2, -1, 0
   double Lx, Ly;
   double c_adv, c_diff, c_nudge;
+  // chromospheric Newtonian cooling: rate, start and width of the density
+  // cutoff (in natural-log orders below ln rho0 at z0), of the height cutoff,
+  // the photospheric ln rho0, the table length (nz+6) and the device copy of
+  // the initial profiles [ln rho0 (nc_n) | ln T0 (nc_n)]
+  double nc_tau, nc_dlr0, nc_dlrw, nc_z0, nc_zw, nc_lnrho_phot;
+  int nc_n;
+  const double* nc_tab;
 };
 
 // Per-substage arguments of the Runge-Kutta update.

@@ -53,6 +53,8 @@ struct PointCtx {
   S uh[2];            // driver u* at (x, y)
   S ah[2];            // A_h* at (x, y)
   double ramp;        // s(t)
+  double nc_cz;       // height cutoff c_z of the Newtonian cooling at this plane
+  double nc_lnT0;     // ln T0 at this plane's height (its reference profile)
 };
 
 // math helpers overloaded on the scalar type
@@ -60,6 +62,30 @@ __device__ inline double s_exp(double a) { return exp(a); }
 __device__ inline float s_exp(float a) { return expf(a); }
 __device__ inline double s_sqrt(double a) { return sqrt(a); }
 __device__ inline float s_sqrt(float a) { return __fsqrt_rn(a); }
+__device__ inline double s_sin(double a) { return sin(a); }
+__device__ inline double value_of(double a) { return a; }
+
+// 1 for x <= start, 0 for x >= start + width, 1/2 [1 - sin(pi (x - start -
+// width/2) / width)] between (the sine cutoffs of the Newtonian cooling)
+template <typename S>
+__device__ inline S sine_cutoff(S x, double start, double width) {
+  const double xv = value_of(x);
+  if (xv <= start) return S(1.0);
+  if (xv >= start + width) return S(0.0);
+  return S(0.5) * (S(1.0) - s_sin(S(M_PI / width) * (x - S(start + 0.5 * width))));
+}
+
+// height cutoff c_z of the Newtonian cooling at plane k (z_k = z0 + k dz)
+__device__ inline double nc_height_cut(const KParams& p, int k) {
+  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(p.z0 + k * p.dz, p.nc_z0, p.nc_zw);
+}
+
+// the initial profiles of the Newtonian cooling through the kernel parameters
+struct ParamNcTable {
+  const KParams& p;
+  __device__ __forceinline__ double lnrho0(int i) const { return p.nc_tab[i]; }
+  __device__ __forceinline__ double lnT0(int i) const { return p.nc_tab[p.nc_n + i]; }
+};
 
 // The radiative-loss table (breakpoints ln T_i, values ln Lambda_i and the
 // slopes between them) as read from the kernel parameters; a kernel may pass
@@ -204,10 +230,58 @@ __device__ __forceinline__ S rhs_radiation(const Src& src, const KParams& p, con
   return rad;
 }
 
+// Chromospheric Newtonian cooling (Sect. 3.1): contribution to d ln T/dt,
+// -tau_t c_rho c_z (1 - T*/T) with ln T* = (ln T0(z) + ln T'(rho)) / 2 and
+// ln T'(rho) = ln T0(z') where ln rho0(z') = ln rho, linear between the
+// bracketing nodes of the (decreasing) ln rho0 table, clamped outside it.  The
+// bracket is found on the value (binary search); the interpolation and the
+// cutoffs are in S, so that dual numbers carry the derivative.  The float
+// path evaluates it in double from the double state.
+template <typename S, class Src, class Tab>
+__device__ __forceinline__ S rhs_newton(const Src& src, const KParams& p, const Tab& tab,
+                                        const PointCtx<S>& pc) {
+  if (p.nc_tau == 0.0 || pc.nc_cz == 0.0) return S(0.0);
+  constexpr bool kFloat = std::is_same<S, float>::value;
+  using T = typename std::conditional<kFloat, double, S>::type;
+  T lr, lT;
+  if constexpr (kFloat) {
+    lr = src.v64(LR);
+    lT = src.v64(LT);
+  } else {
+    lr = src.v(LR);
+    lT = src.v(LT);
+  }
+  const double xv = value_of(lr);
+  const T crho = sine_cutoff(T(p.nc_lnrho_phot) - lr, p.nc_dlr0, p.nc_dlrw);
+  if (value_of(crho) == 0.0) return S(0.0);
+  const int n = p.nc_n;
+  T lTp;
+  if (xv >= tab.lnrho0(0)) {
+    lTp = T(tab.lnT0(0));
+  } else if (xv <= tab.lnrho0(n - 1)) {
+    lTp = T(tab.lnT0(n - 1));
+  } else {
+    int lo = 0, hi = n - 1;   // lnrho0(lo) >= xv > lnrho0(hi)
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tab.lnrho0(mid) >= xv) lo = mid;
+      else hi = mid;
+    }
+    const double x0 = tab.lnrho0(lo), x1 = tab.lnrho0(lo + 1);
+    const double y0 = tab.lnT0(lo), y1 = tab.lnT0(lo + 1);
+    const T w = (T(x0) - lr) / T(x0 - x1);
+    lTp = T(y0) + w * T(y1 - y0);
+  }
+  const T lTs = T(0.5) * (T(pc.nc_lnT0) + lTp);
+  const T term = T(-p.nc_tau * pc.nc_cz) * crho * (T(1.0) - s_exp(lTs - lT));
+  if constexpr (kFloat) return float(term);
+  else return term;
+}
+
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
                                           const KParams& p, const MagState<S>& m, S rad,
-                                          S out[NF]) {
+                                          S nc, S out[NF]) {
   constexpr bool kFloat = std::is_same<S, float>::value;
   const S w = S(pc.w);
   const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
@@ -313,7 +387,7 @@ __device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
 
   {
     const S udT = ux * GlT[0] + uy * GlT[1] + uz * GlT[2];
-    out[LT] = heat + cond - rad - udT - S(p.gm1) * divu + S(p.chi_s) * w * lapT;
+    out[LT] = heat + cond - rad - udT - S(p.gm1) * divu + S(p.chi_s) * w * lapT + nc;
   }
 
   // ================= photospheric nudging and boundary points ================
@@ -333,9 +407,10 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
                                          const KParams& p, S out[NF]) {
   MagState<S> m;
   const S rad = rhs_radiation<S>(src, p, ParamRadTable{p});
+  const S nc = rhs_newton<S>(src, p, ParamNcTable{p}, pc);
   rhs_magnetic<S>(src, pc, p, out, m);
   CMHD_FENCE();
-  rhs_fluid<S>(src, pc, p, m, rad, out);
+  rhs_fluid<S>(src, pc, p, m, rad, nc, out);
 }
 
 }  // namespace cmhd

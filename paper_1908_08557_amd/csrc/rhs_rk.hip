@@ -184,6 +184,14 @@ struct LdsRadTable {
   __device__ __forceinline__ double slope(int i) const { return t[2 * CMHD_MAX_RAD + i]; }
 };
 
+// The initial profiles of the Newtonian cooling copied into LDS.
+struct LdsNcTable {
+  const double* t;   // [ln rho0 (n)][ln T0 (n)]
+  int n;
+  __device__ __forceinline__ double lnrho0(int i) const { return t[i]; }
+  __device__ __forceinline__ double lnT0(int i) const { return t[n + i]; }
+};
+
 // Source for rhs_eval: the derivatives of A are read from the staged plane on
 // demand (rolled component loop, few registers), everything else from the
 // inputs gathered into registers (indices are compile-time constants).  The
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(256) void k_zderiv(const double* __restrict__ f,
 }
 
 // ---------------------------------------------------------------------------
-template <typename Real, bool SOLAR, bool READ_DF, bool WRITE_DF>
+template <typename Real, bool SOLAR, bool READ_DF, bool WRITE_DF, bool NEWTON>
 __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                                const Real* __restrict__ dz,
                                                double* __restrict__ fo,
@@ -317,6 +325,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
   __shared__ __align__(16) double sDx[NDX][DXP];  // D1_x (unscaled) on tile + y halo
   __shared__ __align__(16) double sDF[NF][NT];    // RK register, own
   __shared__ __align__(16) double sRad[3 * CMHD_MAX_RAD];
+  // Newtonian cooling profiles (only the NEWTON variant has the term)
+  __shared__ __align__(16) double sNC[NEWTON ? 2 * CMHD_MAX_NC_TABLE : 1];
 
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
@@ -367,6 +377,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     sRad[CMHD_MAX_RAD + tid] = p.rad_lnL[tid];
     sRad[2 * CMHD_MAX_RAD + tid] = p.rad_slope[tid];
   }
+  if (NEWTON)
+    for (int i = tid; i < 2 * p.nc_n; i += NT) sNC[i] = p.nc_tab[i];
   copy_plane(kbeg, true);
   copy_plane(kbeg, false);
   copies_barrier();
@@ -442,6 +454,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     pc.bottom = SOLAR && k == 0;
     pc.top = SOLAR && k == p.nz - 1;
     pc.ramp = st.ramp;
+    pc.nc_cz = NEWTON ? nc_height_cut(p, k) : 0.0;
+    pc.nc_lnT0 = NEWTON ? sNC[p.nc_n + k + NG] : 0.0;
     if (SOLAR && k == 0) {
       pc.uh[0] = Real(uh[oc]);
       pc.uh[1] = Real(uh[sp + oc]);
@@ -455,6 +469,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     Real out[NF];
     MagState<Real> mag;
     const Real rad = rhs_radiation<Real>(src, p, LdsRadTable{sRad});
+    const Real nc = NEWTON ? rhs_newton<Real>(src, p, LdsNcTable{sNC, p.nc_n}, pc) : Real(0.0);
     rhs_magnetic<Real>(src, pc, p, out, mag);
     lds_barrier();
 
@@ -462,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     if (k + 1 < kend) copy_plane(k + 1, true);
 
     // ---- 2b: fluid part of the right-hand side, from registers
-    rhs_fluid<Real>(src, pc, p, mag, rad, out);
+    rhs_fluid<Real>(src, pc, p, mag, rad, nc, out);
 
     copies_barrier();
 
@@ -520,7 +535,7 @@ hipError_t launch_zderiv_typed(const KParams& p, const double* f, void* dz, int 
   return hipGetLastError();
 }
 
-template <typename Real, bool SOLAR>
+template <typename Real, bool SOLAR, bool NEWTON>
 hipError_t launch_typed(const KParams& p, int stage, const double* f, const void* dzv,
                         double* fo, double* dF, const double* uh, const double* ah, StageArgs st,
                         const ChunkPlan& cp, int chunk0, int nchunks, hipStream_t s) {
@@ -532,15 +547,27 @@ hipError_t launch_typed(const KParams& p, int stage, const double* f, const void
   dim3 grid(unsigned(tm.ntx * tm.nty * nchunks));
   const Real* dz = static_cast<const Real*>(dzv);
   if (stage == 0)
-    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, false, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, cp.kchunk, chunk0, tm);
+    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, false, true, NEWTON>), grid, dim3(NT), 0, s, f, dz,
+                       fo, dF, uh, ah, p, st, cp.kchunk, chunk0, tm);
   else if (stage == 1)
-    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, true>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, cp.kchunk, chunk0, tm);
+    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, true, NEWTON>), grid, dim3(NT), 0, s, f, dz,
+                       fo, dF, uh, ah, p, st, cp.kchunk, chunk0, tm);
   else
-    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, false>), grid, dim3(NT), 0, s, f, dz, fo, dF,
-                       uh, ah, p, st, cp.kchunk, chunk0, tm);
+    hipLaunchKernelGGL((k_rhs_rk<Real, SOLAR, true, false, NEWTON>), grid, dim3(NT), 0, s, f, dz,
+                       fo, dF, uh, ah, p, st, cp.kchunk, chunk0, tm);
   return hipGetLastError();
+}
+
+// the Newtonian cooling variant is built for the solar (stratified) mode only
+template <typename Real>
+hipError_t launch_prec(const KParams& p, int stage, const double* f, const void* dz, double* fo,
+                       double* dF, const double* uh, const double* ah, StageArgs st,
+                       const ChunkPlan& cp, int chunk0, int nchunks, hipStream_t s) {
+  if (p.solar && p.nc_tau != 0.0)
+    return launch_typed<Real, true, true>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
+  if (p.solar)
+    return launch_typed<Real, true, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
+  return launch_typed<Real, false, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
 }
 
 }  // namespace
@@ -582,12 +609,8 @@ hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f,
                          StageArgs st, const ChunkPlan& cp, int chunk0, int nchunks,
                          hipStream_t s) {
   if (prec == CMHD_FP32_SPLIT)
-    return p.solar
-               ? launch_typed<float, true>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s)
-               : launch_typed<float, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
-  return p.solar
-             ? launch_typed<double, true>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s)
-             : launch_typed<double, false>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
+    return launch_prec<float>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
+  return launch_prec<double>(p, stage, f, dz, fo, dF, uh, ah, st, cp, chunk0, nchunks, s);
 }
 
 hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,

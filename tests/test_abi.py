@@ -36,7 +36,7 @@ def test_struct_layout_matches_header():
     # cmhd_grid: 3 ints, 4 doubles, 2 ints (natural alignment)
     assert ctypes.sizeof(cmhd.CmhdGrid) == 56
     # cmhd_params: 8 + 3 + 1 + 9 doubles, int (padded), 2*16 doubles, 5 doubles
-    assert ctypes.sizeof(cmhd.CmhdParams) == (21 * 8) + 8 + 32 * 8 + 5 * 8
+    assert ctypes.sizeof(cmhd.CmhdParams) == (21 * 8) + 8 + 32 * 8 + 5 * 8 + 5 * 8
     assert cmhd.CmhdParams.n_rad.offset == 21 * 8
 
 

@@ -46,7 +46,15 @@ CASES = {
     "strat32x32x12": lambda: W.small_stratified(32, 32, 12, t_ramp=0.06),
     "strat32x16x10_norad": lambda: _norad(W.small_stratified(32, 16, 10, Lxy=10.0, z1=8.0)),
     "periodic16": lambda: W.periodic_box(16, nmodes=6, amp_u=1e-2),
+    "strat32x32x24_newton": lambda: _newton(),
 }
+
+
+def _newton():
+    # the Newtonian cooling on, with the perturbed chromosphere of the
+    # parity test
+    from test_gpu_parity import newton_case
+    return newton_case()
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -77,7 +85,7 @@ def test_dot_product_tlm_vs_adjoint(case):
     assert float(dy[~mask].abs().max()) == 0.0 and float(xbar[~mask].abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("case", ["strat32x32x12", "periodic16"])
+@pytest.mark.parametrize("case", ["strat32x32x12", "periodic16", "strat32x32x24_newton"])
 def test_tlm_matches_oracle_complex_step(case):
     import torch
     w = CASES[case]()

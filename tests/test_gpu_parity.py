@@ -83,6 +83,67 @@ def test_strat64_one_step():
     assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12, "strat64 1 step")
 
 
+def newton_case(nx=32, ny=32, nz=24, norad=False):
+    """Stratified box with the chromospheric Newtonian cooling on and smooth
+    seeded perturbations of ln T and ln rho in the planes k = 1..8, so that
+    T != T* and rho != rho0(z) where the cooling acts (both cutoffs reached:
+    the density falls through the transition region above 2 Mm)."""
+    w = W.enable_newton_cooling(W.small_stratified(nx, ny, nz, Lxy=20.0, z1=20.0))
+    if norad:
+        # radiation and conduction off: dt is no longer limited by them, so
+        # the cooling (tau_t dt up to ~1) changes ln T strongly in one step
+        w.params.update(rad_lnT=np.zeros(0), rad_lnL=np.zeros(0), kappa0=0.0)
+    rng = np.random.default_rng(11)
+    x = np.arange(nx) / nx
+    y = np.arange(ny) / ny
+    for f, amp in ((6, 0.3), (7, 0.08)):
+        pert = np.zeros((ny, nx))
+        for _ in range(4):
+            kx, ky = rng.integers(1, 3, size=2)
+            ph = rng.uniform(0, 2 * np.pi)
+            pert += np.cos(2 * np.pi * (kx * x[None, :] + ky * y[:, None]) + ph)
+        for k in range(1, 9):
+            w.state[f, NG + k] += amp * pert * (1.0 - k / 9.0)
+    return w
+
+
+@pytest.mark.parametrize("norad", [False, True])
+def test_newton_cooling_one_step(norad):
+    w = newton_case(norad=norad)
+    dt = oracle_dt(w)
+    print(f"[case] Newtonian cooling one step (norad={norad}, dt={dt:.3e})", flush=True)
+    assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
+                  f"newton 1 step norad={norad}")
+
+
+def test_newton_cooling_ten_steps_and_split():
+    import torch
+    from paper_1908_08557_amd import cmhd
+    w = newton_case()
+    print("[case] Newtonian cooling ten steps (FP64) and two steps (FP32-split)", flush=True)
+    dt = oracle_dt(w)
+    assert_parity(gpu_run(w, 10, dt), oracle_run(w, 10, dt), True, 1e-11, "newton 10 steps")
+    s = cmhd.solver_for(w, "fp32_split")
+    st = s.new_state(w.state)
+    t = 0.0
+    for _ in range(2):
+        t, _ = s.rk3_step(st, t, dt)
+    assert_parity(st.cpu().numpy(), oracle_run(w, 2, dt), True, 2e-6, "newton 2 steps split")
+
+
+def test_newton_cooling_dt_limit():
+    # tau_t enters the nudging limit of the time step like tau_u and tau_A
+    import torch
+    from paper_1908_08557_amd import cmhd
+    w = newton_case()
+    w.params.update(nc_tau=5e4)
+    print("[case] Newtonian cooling dt limit", flush=True)
+    s = cmhd.solver_for(w)
+    dt = s.cfl_dt(s.new_state(w.state))
+    assert dt == pytest.approx(oracle_dt(w), rel=1e-12)
+    assert dt <= w.params["c_nudge"] / 5e4 * (1 + 1e-12)
+
+
 _PIPELINED = {}   # oracle result shared by the two precisions
 
 
