@@ -360,6 +360,17 @@ def ramp(t, t_ramp):
     return min(1.0, t / t_ramp)
 
 
+def driver_target(drv, t):
+    """u* of eq. (5) at time t: the single target drv["uh"], or, for a pair of
+    snapshots (drv["uh0"] at drv["t0"], drv["uh1"] at drv["t1"]), their linear
+    interpolation in time with the weight clipped to [0, 1] (reading: the
+    coronal run interpolates between granulation snapshots, Sect. 2.3)."""
+    if "uh1" not in drv:
+        return drv["uh"]
+    w = min(1.0, max(0.0, (t - drv["t0"]) / (drv["t1"] - drv["t0"])))
+    return drv["uh0"] + w * (drv["uh1"] - drv["uh0"])
+
+
 def rhs(F, t, grid, par, drv):
     """Right-hand side at every interior zone, from a ghost-filled state F.
 
@@ -486,7 +497,7 @@ def rhs(F, t, grid, par, drv):
     Rgh = None
     if solar:
         s = ramp(t, par["t_ramp"])
-        ustar, astar = drv["uh"], drv["ah"]
+        ustar, astar = driver_target(drv, t), drv["ah"]
         # nudging toward the driver, eq. (5), layers k = 0 .. -3
         for c in (0, 1):
             R[UX + c, 0] = R[UX + c, 0] - par["tau_u"] * (val[UX + c][0] - s * ustar[c])

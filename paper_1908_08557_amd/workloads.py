@@ -339,6 +339,22 @@ def ar1024():
     return stratified_box(1024, 1024, 256, 64.0, 50.0, 32, 11, 3, "ar1024")
 
 
+def granulation_randoms(n: int, seed: int):
+    """Random pools of the granulation driver: n uniforms in [0, 1) (birth
+    positions) and 2n standard-normal draws truncated to [-1, 1] by rejection
+    (lifetime and amplitude variations)."""
+    rng = np.random.default_rng(seed)
+    unif = rng.random(n)
+    xi = np.empty(2 * n)
+    k = 0
+    while k < 2 * n:
+        d = rng.standard_normal(4 * n)
+        d = d[np.abs(d) <= 1.0][: 2 * n - k]
+        xi[k:k + d.size] = d
+        k += d.size
+    return unif, xi
+
+
 def driver_reseed(w: Workload, seed: int):
     """A fresh driver target for the same box (used every 10 steps)."""
     g = w.grid
