@@ -12,7 +12,9 @@ re-seeded every 10 steps (device-resident targets, set with cmhd_set_driver).
 
 Prints one JSON line: the FP64 throughput (zone-updates/s) as `value`, the
 FP32-split form beside it, the HBM roofline of the fused kernel from HIP
-events around its launches, and the CPU oracle timed on a bounded sample.
+events around its launches, the granulation driver's cost per snapshot on the
+same photospheric plane (outside the timed steps), and the CPU oracle timed on
+a bounded sample.
 """
 from __future__ import annotations
 
@@ -102,6 +104,49 @@ def run_gpu(w, precision, steps, warmup, drivers):
                 step_GBs=BYTES_PER_ZONE_STEP * zones / (elapsed / steps) / 1e9)
 
 
+def driver_bench(w, dt, ms_per_step, reps=5):
+    """The granulation driver on the workload's photospheric plane: host
+    bookkeeping of the first fill and of a 10 s update, and the GPU snapshot
+    (render + eq. 3 enhancement + eq. 4 rescaling), timed with HIP events on
+    the stream the driver object launches on."""
+    import torch
+    from paper_1908_08557_amd import cmhd
+    from paper_1908_08557_amd import workloads as W
+    g = w.grid
+    p = dict(nx=g["nx"], ny=g["ny"], Lx=g["Lx"], Ly=g["Ly"], r_gran=0.8, r_lane=1.04,
+             r_excl=0.64, t_gran=0.3, v0=1.028, vmin_frac=0.78, life_var=0.10, amp_var=0.15,
+             f_rot=5.0)
+    n_pool = int(4 * g["Lx"] * g["Ly"]) + 1000
+    u, xi = W.granulation_randoms(n_pool, 31)
+    drv = cmhd.Granulation(p)
+    t0 = time.perf_counter()
+    b0 = drv.update(0.0, u, xi)
+    fill_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    b1 = drv.update(0.01, u[b0:], xi[2 * b0:])     # 10 s later
+    update_ms = (time.perf_counter() - t0) * 1e3
+    n = len(drv.granules())
+    out = torch.empty((2, g["ny"], g["nx"]), dtype=torch.float64, device="cuda")
+    drv.velocity(0.01, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        drv.velocity(0.01, out)
+    e1.record()
+    torch.cuda.synchronize()
+    vel_ms = e0.elapsed_time(e1) / reps
+    finite = bool(torch.isfinite(out).all().item())
+    drv.close()
+    steps_per_snapshot = 0.01 / dt            # one snapshot every 10 s of model time
+    return {"plane": f"{g['nx']}x{g['ny']} over {g['Lx']}x{g['Ly']} Mm", "granules": n,
+            "births_first_fill": b0, "births_10s_update": b1,
+            "fill_ms_host": fill_ms, "update_ms_host": update_ms, "snapshot_ms_gpu": vel_ms,
+            "steps_per_snapshot": steps_per_snapshot,
+            "share_of_step_time": (update_ms + vel_ms) / (steps_per_snapshot * ms_per_step),
+            "finite": finite}
+
+
 def cpu_baseline():
     """The oracle as it stands, on a bounded sample: a 128 x 128 x 64 box with
     the 512^2 x 256 box's grid spacing and physics, eight RK3 steps (about
@@ -132,6 +177,7 @@ def main():
     ap.add_argument("--workload", default="strat512")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-driver", action="store_true", help="skip the granulation-driver timing")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +253,10 @@ def main():
         out["roofline"]["traffic_source"] = tr["profile"]
         out["roofline"]["valu_busy_pct"] = tr["valu_busy_pct_fused"]
     out["finite"] = all(v["finite"] for v in res.values())
+    if not args.no_driver and g["zbc"] == "solar":
+        log("[bench] granulation driver")
+        out["driver"] = driver_bench(w, r["dt"], r["ms_per_step"])
+        log(f"[bench] driver: {out['driver']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -167,6 +167,19 @@ cmhd_status cmhd_set_stream(cmhd_ctx* ctx, void* stream);
 cmhd_status cmhd_set_driver(cmhd_ctx* ctx, const double* uh, const double* bz,
                             const double* ah);
 
+/* Photospheric driver as two snapshots (Sect. 2.3: the coronal run reads
+ * granulation snapshots and interpolates between them in time).  uh0, uh1:
+ * device [2][ny][nx], u* at times t0 < t1 (both finite), copied on the
+ * context stream.  From then on the target of eq. (5) at a substage time t is
+ * u*_0 + w (u*_1 - u*_0), w = (t - t0) / (t1 - t0) clipped to [0, 1],
+ * formed by a small kernel before every substage.  A_h* is not changed.  A
+ * later cmhd_set_driver returns to a single target.  With a snapshot pair the
+ * tangent and adjoint steps accept no driver perturbation or cotangent
+ * (duh, uhbar must be NULL; CMHD_EINVAL otherwise).  EINVAL for NULL
+ * snapshots or t1 <= t0. */
+cmhd_status cmhd_set_driver_snapshots(cmhd_ctx* ctx, const double* uh0, double t0,
+                                      const double* uh1, double t1);
+
 /* Fill every derived ghost plane of the device state in place (solar: the
  * rules listed at the top; periodic: plane copies).  t is unused today (the
  * rules do not depend on time) and kept for time-dependent boundaries. */
@@ -248,6 +261,80 @@ cmhd_status cmhd_profile_read(cmhd_ctx* ctx, int which, double* ms, int* launche
 
 const char* cmhd_last_error(const cmhd_ctx* ctx);
 void cmhd_destroy(cmhd_ctx* ctx);
+
+/* ---- photospheric granulation driver (Sect. 2.3, eqs. 1-4) ----
+ * A 2-D run on the photospheric pixel grid that produces driver snapshots
+ * u*(x, y) for cmhd_set_driver / cmhd_set_driver_snapshots.  Granules of
+ * radius r_gran whose radial outflow extends, through the lane zone, to
+ * r_lane fill the plane by random sequential addition: a pixel (x_i = i dx,
+ * y_j = j dy) is free when every living centre lies at least r_excl away, and
+ * each birth takes the floor(u n)-th free pixel in raster order (y slowest)
+ * for the next uniform u of the caller's pool, n the number of free pixels,
+ * until none is free.  A granule born at t0 has lifetime
+ * T = t_gran (1 + life_var xi_T), amplitude v_max = v0 (1 + amp_var xi_v),
+ * t_max = T sqrt(|ln(v_min / v_max)|) (eq. 1), v_min = vmin_frac v0, speed
+ * v(t) = v_max exp(-((t - t0 - t_max) / T)^2) (eq. 2), and ceases to exist at
+ * the first update with t > t0 + 2 t_max (where v has fallen below v_min).
+ * Its velocity is v(t) g(r) r_hat, g = r / r_gran inside r_gran,
+ * (1 + cos(pi (r - r_gran) / (r_lane - r_gran))) / 2 in the lane zone, 0
+ * beyond, nearest periodic image; the fields of all granules add up.  The
+ * snapshot is that granular field plus f_rot times its rotational
+ * (divergence-free) part filtered by exp(-(2 |k| / k_N)^4) (eq. 3; k = 0 and
+ * the Nyquist row and column dropped, k_N = pi / max(dx, dy)), rescaled to
+ * the rms of the granular field (eq. 4).  With an external velocity field the
+ * centres move with it (forward Euler since the previous update, bilinear
+ * sample at the centre, positions wrapped into [0, L)).
+ * Random draws are inputs: the caller's pools unif (uniforms in [0, 1), one
+ * per birth) and xi (variations in [-1, 1], two per birth: xi_T, xi_v).
+ * Ownership and streams as for the MHD context: the caller allocates and
+ * binds the workspace; kernels run on the object's stream. */
+typedef struct cmhd_gran_params {
+  int nx, ny;               /* pixel grid, powers of two in [16, 1024] */
+  double Lx, Ly;            /* periodic extent */
+  double r_gran;            /* granule radius (0.8 Mm) */
+  double r_lane;            /* outer edge of the lane zone (1.04 Mm), > r_gran */
+  double r_excl;            /* no birth closer to a living centre (0.64 Mm) */
+  double t_gran;            /* mean lifetime T_gran (5 min) */
+  double v0;                /* mean amplitude (1.028 km/s) */
+  double vmin_frac;         /* v_min / v0 (0.78), below 1 - amp_var */
+  double life_var;          /* lifetime variation (0.10), in [0, 1) */
+  double amp_var;           /* amplitude variation (0.15), in [0, 1) */
+  double f_rot;             /* vorticity factor (5) */
+} cmhd_gran_params;
+
+typedef struct cmhd_gran cmhd_gran;
+
+/* Create an empty population.  stream: hipStream_t of every later launch.
+ * EINVAL on bad sizes or parameters. */
+cmhd_status cmhd_gran_create(const cmhd_gran_params* params, void* stream, cmhd_gran** out);
+
+/* Device workspace: the granule table (up to the hexagonal packing bound
+ * Lx Ly / (sqrt(3)/2 r_excl^2) granules), two complex Fourier planes and
+ * reduction scratch.  Caller-allocated, 256-byte aligned, bound once. */
+size_t cmhd_gran_workspace_bytes(const cmhd_gran* g);
+cmhd_status cmhd_gran_bind_workspace(cmhd_gran* g, void* dev_ptr, size_t bytes);
+
+/* Advance the population to time t (not before the previous update): advect
+ * the centres with vext_host ([2][ny][nx] host memory, or NULL: centres stay
+ * put), remove the granules that have ended, refill.  Births consume
+ * unif[0..], xi[0..] (host memory, n_pool uniforms and 2 n_pool variations);
+ * *births receives their number.  The host work is sequential; the granule
+ * table is then copied to the device (synchronous).  EINVAL when the pool runs
+ * out (the granules born until then are kept). */
+cmhd_status cmhd_gran_update(cmhd_gran* g, double t, const double* vext_host, const double* unif,
+                             const double* xi, long long n_pool, long long* births);
+
+/* Driver snapshot at time t from the current population into device
+ * uh [2][ny][nx]: granular field, eq. (3) enhancement, eq. (4) rescaling
+ * (a zero field when there is no granule).  Asynchronous. */
+cmhd_status cmhd_gran_velocity(cmhd_gran* g, double t, double* uh);
+
+/* Host copy of the living granules, rows (x, y, t0, T, v_max, t_max) in birth
+ * order, at most cap rows; *n receives the population size. */
+cmhd_status cmhd_gran_list(const cmhd_gran* g, double* host, int cap, int* n);
+
+const char* cmhd_gran_last_error(const cmhd_gran* g);
+void cmhd_gran_destroy(cmhd_gran* g);
 
 #ifdef __cplusplus
 }

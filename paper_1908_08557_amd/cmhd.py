@@ -43,6 +43,13 @@ class CmhdParams(ctypes.Structure):
         ("nc_tau", "nc_lnrho_magn", "nc_lnrho_width", "nc_z_max", "nc_z_width")]
 
 
+class CmhdGranParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int)] + [
+        (n, ctypes.c_double) for n in
+        ("Lx", "Ly", "r_gran", "r_lane", "r_excl", "t_gran", "v0", "vmin_frac", "life_var",
+         "amp_var", "f_rot")]
+
+
 class CmhdError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"cmhd error {code}: {msg}")
@@ -70,6 +77,7 @@ def load():
         "cmhd_bind_workspace": (I, [P, P, S]),
         "cmhd_set_stream": (I, [P, P]),
         "cmhd_set_driver": (I, [P, P, P, P]),
+        "cmhd_set_driver_snapshots": (I, [P, P, D, P, D]),
         "cmhd_fill_ghosts": (I, [P, P, D]),
         "cmhd_rk3_step": (I, [P, P, ctypes.POINTER(D), D, ctypes.POINTER(D)]),
         "cmhd_cfl_dt": (I, [P, P, ctypes.POINTER(D)]),
@@ -86,6 +94,15 @@ def load():
         "cmhd_profile_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I)]),
         "cmhd_last_error": (ctypes.c_char_p, [P]),
         "cmhd_destroy": (None, [P]),
+        "cmhd_gran_create": (I, [ctypes.POINTER(CmhdGranParams), P, ctypes.POINTER(P)]),
+        "cmhd_gran_workspace_bytes": (S, [P]),
+        "cmhd_gran_bind_workspace": (I, [P, P, S]),
+        "cmhd_gran_update": (I, [P, D, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D),
+                                 ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
+        "cmhd_gran_velocity": (I, [P, D, P]),
+        "cmhd_gran_list": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+        "cmhd_gran_last_error": (ctypes.c_char_p, [P]),
+        "cmhd_gran_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -98,11 +115,15 @@ def load():
 def exported_symbols():
     """Names the binding expects the library to export."""
     return ["cmhd_init_grid", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
-            "cmhd_set_stream", "cmhd_set_driver", "cmhd_fill_ghosts", "cmhd_rk3_step",
+            "cmhd_set_stream", "cmhd_set_driver", "cmhd_set_driver_snapshots",
+            "cmhd_fill_ghosts", "cmhd_rk3_step",
             "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_bz_plane", "cmhd_check_finite",
             "cmhd_adjoint_workspace_bytes", "cmhd_bind_adjoint_workspace", "cmhd_rk3_step_jvp",
             "cmhd_rk3_step_vjp", "cmhd_bz_plane_vjp",
-            "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy"]
+            "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy",
+            "cmhd_gran_create", "cmhd_gran_workspace_bytes", "cmhd_gran_bind_workspace",
+            "cmhd_gran_update", "cmhd_gran_velocity", "cmhd_gran_list", "cmhd_gran_last_error",
+            "cmhd_gran_destroy"]
 
 
 def make_grid(grid: dict, precision: str = "fp64") -> CmhdGrid:
@@ -205,6 +226,17 @@ class Solver:
         self._drv = (dev(uh), dev(bz), dev(ah))   # kept alive until the stream passes
         self._check(self.lib.cmhd_set_driver(self.ctx, _ptr(self._drv[0]), _ptr(self._drv[1]),
                                              _ptr(self._drv[2])))
+
+    def set_driver_snapshots(self, uh0, t0, uh1, t1):
+        """Nudging target interpolated linearly in time between u*_0 at t0 and
+        u*_1 at t1 (device or host arrays [2, ny, nx])."""
+        self._stream()
+        dev = lambda a: torch.as_tensor(
+            np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a,
+            dtype=torch.float64, device=self.device).contiguous()
+        self._drv = (dev(uh0), dev(uh1))
+        self._check(self.lib.cmhd_set_driver_snapshots(self.ctx, _ptr(self._drv[0]), float(t0),
+                                                       _ptr(self._drv[1]), float(t1)))
 
     def fill_ghosts(self, state, t=0.0):
         self._stream()
@@ -321,6 +353,85 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.cmhd_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Granulation:
+    """One granulation-driver object of the library (photospheric plane)."""
+
+    FIELDS = ("r_gran", "r_lane", "r_excl", "t_gran", "v0", "vmin_frac", "life_var", "amp_var",
+              "f_rot")
+
+    def __init__(self, params: dict, device: str = "cuda"):
+        self.lib = load()
+        self.device = torch.device(device)
+        q = CmhdGranParams()
+        q.nx, q.ny = int(params["nx"]), int(params["ny"])
+        q.Lx, q.Ly = float(params["Lx"]), float(params["Ly"])
+        for n in self.FIELDS:
+            setattr(q, n, float(params[n]))
+        self._q = q
+        self.shape = (2, q.ny, q.nx)
+        obj = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.cmhd_gran_create(ctypes.byref(q), ctypes.c_void_p(stream), ctypes.byref(obj))
+        if rc != CMHD_OK:
+            raise CmhdError(rc, "cmhd_gran_create: invalid parameters")
+        self.obj = obj
+        nbytes = self.lib.cmhd_gran_workspace_bytes(obj)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._check(self.lib.cmhd_gran_bind_workspace(obj, ctypes.c_void_p(base + (-base) % 256),
+                                                      nbytes))
+
+    def _check(self, rc):
+        if rc != CMHD_OK:
+            raise CmhdError(rc, self.lib.cmhd_gran_last_error(self.obj).decode())
+
+    def update(self, t, unif, xi, vext=None):
+        """Advance the population to t; returns the number of births (the
+        draws consumed from the front of unif and, two each, of xi)."""
+        dp = ctypes.POINTER(ctypes.c_double)
+        u = np.ascontiguousarray(unif, dtype=np.float64)
+        x = np.ascontiguousarray(xi, dtype=np.float64)
+        n_pool = min(u.size, x.size // 2)
+        v = None if vext is None else np.ascontiguousarray(vext, dtype=np.float64)
+        if v is not None and v.shape != self.shape:
+            raise ValueError(f"vext must have shape {self.shape}")
+        births = ctypes.c_longlong(0)
+        self._check(self.lib.cmhd_gran_update(
+            self.obj, float(t), None if v is None else v.ctypes.data_as(dp), u.ctypes.data_as(dp),
+            x.ctypes.data_as(dp), n_pool, ctypes.byref(births)))
+        return births.value
+
+    def velocity(self, t, out=None):
+        """Driver snapshot at time t (runs on the stream current at creation)."""
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        if tuple(out.shape) != self.shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor {self.shape}")
+        self._check(self.lib.cmhd_gran_velocity(self.obj, float(t), _ptr(out)))
+        return out
+
+    def granules(self):
+        """Living granules as rows (x, y, t0, T, v_max, t_max)."""
+        n = ctypes.c_int(0)
+        self._check(self.lib.cmhd_gran_list(self.obj, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), 6))
+        self._check(self.lib.cmhd_gran_list(
+            self.obj, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+            ctypes.byref(n)))
+        return out[:n.value]
+
+    def close(self):
+        if getattr(self, "obj", None):
+            self.lib.cmhd_gran_destroy(self.obj)
+            self.obj = None
 
     def __del__(self):
         try:

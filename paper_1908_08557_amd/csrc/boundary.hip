@@ -417,6 +417,15 @@ __global__ void k_sum_abs(const KParams p, const double* __restrict__ a, double*
   }
 }
 
+// nudging target between two driver snapshots: u0 + w (u1 - u0)
+__global__ void k_driver_interp(long long n, const double* __restrict__ u0,
+                                const double* __restrict__ u1, double w,
+                                double* __restrict__ uh) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    uh[i] = u0[i] + w * (u1[i] - u0[i]);
+}
+
 int grid_for(long long n) {
   long long b = (n + 255) / 256;
   return int(b < 8192 ? (b > 0 ? b : 1) : 8192);
@@ -486,6 +495,13 @@ hipError_t launch_bz_plane(const KParams& p, const double* f, double zq, double*
 hipError_t launch_finite_check(const KParams& p, const double* f, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_finite, dim3(grid_for((long long)NF * p.nz * p.splane)), dim3(256), 0, s,
                      p, f, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_driver_interp(const KParams& p, const double* u0, const double* u1, double w,
+                                double* uh, hipStream_t s) {
+  const long long n = 2 * p.splane;
+  hipLaunchKernelGGL(k_driver_interp, dim3(grid_for(n)), dim3(256), 0, s, n, u0, u1, w, uh);
   return hipGetLastError();
 }
 

@@ -22,7 +22,11 @@ struct cmhd_ctx {
   double* W1 = nullptr;   // stage buffers
   double* W2 = nullptr;
   double* dF = nullptr;   // RK register
-  double* uh = nullptr;   // driver u*      [2][ny][nx]
+  double* uh = nullptr;   // driver u*      [2][ny][nx] (of the current substage)
+  double* u0 = nullptr;   // driver snapshots [2][ny][nx] each, at snap_t0 and snap_t1
+  double* u1 = nullptr;
+  bool snap = false;
+  double snap_t0 = 0.0, snap_t1 = 1.0;
   double* ah = nullptr;   // A_h* target    [2][ny][nx]
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
@@ -84,6 +88,8 @@ size_t ws_layout(const cmhd_ctx* c, size_t off[16]) {
   off[6] = o; o += 256;                                          // reductions
   off[7] = o; o += align256(zderiv_bytes(c->kp, c->grid.prec));  // z derivatives
   off[8] = o; o += align256(2 * size_t(c->kp.nc_n) * sizeof(double));   // ln rho0, ln T0
+  off[9] = o; o += align256(2 * plane * sizeof(double));         // driver snapshot 0
+  off[10] = o; o += align256(2 * plane * sizeof(double));        // driver snapshot 1
   return o;
 }
 
@@ -330,6 +336,9 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->red = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
   c->dz = c->ws + off[7];
   c->nc_dev = reinterpret_cast<double*>(c->ws + off[8]);
+  c->u0 = reinterpret_cast<double*>(c->ws + off[9]);
+  c->u1 = reinterpret_cast<double*>(c->ws + off[10]);
+  c->snap = false;
   c->kp.nc_tab = c->nc_dev;
   // driver targets start at zero; the stage buffers are fully written before use
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
@@ -357,6 +366,7 @@ cmhd_status cmhd_set_driver(cmhd_ctx* c, const double* uh, const double* bz, con
   hipError_t e = hipMemcpyAsync(c->uh, uh, 2 * plane * sizeof(double), hipMemcpyDeviceToDevice,
                                 c->stream);
   if (e != hipSuccess) return hip_check(c, e, "driver copy");
+  c->snap = false;
   if (ah) {
     e = hipMemcpyAsync(c->ah, ah, 2 * plane * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "driver copy");
@@ -376,6 +386,24 @@ cmhd_status cmhd_set_driver(cmhd_ctx* c, const double* uh, const double* bz, con
     e = launch_ah_from_bz(c->kp, bz, c->ah, c->fft, c->stream);
     if (e != hipSuccess) return hip_check(c, e, "A_h* from B_z");
   }
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_set_driver_snapshots(cmhd_ctx* c, const double* uh0, double t0,
+                                      const double* uh1, double t1) {
+  if (!c) return CMHD_EINVAL;
+  cmhd_status st = need_ws(c);
+  if (st != CMHD_OK) return st;
+  if (!uh0 || !uh1) return fail(c, CMHD_EINVAL, "a driver snapshot is NULL");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0))
+    return fail(c, CMHD_EINVAL, "snapshot times must be finite with t1 > t0");
+  const size_t bytes = 2 * size_t(c->grid.nx) * size_t(c->grid.ny) * sizeof(double);
+  hipError_t e = hipMemcpyAsync(c->u0, uh0, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->u1, uh1, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "driver snapshot copy");
+  c->snap = true;
+  c->snap_t0 = t0;
+  c->snap_t1 = t1;
   return CMHD_OK;
 }
 
@@ -414,6 +442,14 @@ hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which)
   hipError_t e = hipEventRecord(ev.second, c->stream);
   c->ev_pending[which].push_back(ev);
   return e;
+}
+
+// the nudging target of a substage at time ts (snapshot pair: interpolated
+// into the u* buffer; single target: nothing to do)
+hipError_t driver_at(cmhd_ctx* c, double ts) {
+  if (!c->kp.solar || !c->snap) return hipSuccess;
+  const double w = std::min(1.0, std::max(0.0, (ts - c->snap_t0) / (c->snap_t1 - c->snap_t0)));
+  return launch_driver_interp(c->kp, c->u0, c->u1, w, c->uh, c->stream);
 }
 
 // one substage from src to dst (ghosts of src already filled): z-derivative
@@ -482,7 +518,8 @@ cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, doub
     st = do_fill(c, src[s]);
     if (st != CMHD_OK) return st;
     StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, *t + RK_C[s] * dt)};
-    hipError_t e = substage(c, s, src[s], dst[s], c->dF, a);
+    hipError_t e = driver_at(c, *t + RK_C[s] * dt);
+    if (e == hipSuccess) e = substage(c, s, src[s], dst[s], c->dF, a);
     if (e != hipSuccess) return hip_check(c, e, "rk3 substage launch");
   }
   *t += dt;
@@ -498,7 +535,9 @@ cmhd_status cmhd_eval_rhs(cmhd_ctx* c, double* state, double t, double* rhs) {
   if (st != CMHD_OK) return st;
   // one substage with alpha = 0, beta = 0, dt = 1: dF = RHS, f_next = f (into W1)
   StageArgs a{0.0, 0.0, 1.0, ramp(c, t)};
-  return hip_check(c, substage(c, 0, state, c->W1, rhs, a), "eval_rhs launch");
+  hipError_t e = driver_at(c, t);
+  if (e == hipSuccess) e = substage(c, 0, state, c->W1, rhs, a);
+  return hip_check(c, e, "eval_rhs launch");
 }
 
 cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, double* dst,
@@ -573,7 +612,9 @@ cmhd_status fwd_stage(cmhd_ctx* c, int s, double* src, double* dst, double t, do
   cmhd_status st = do_fill(c, src);
   if (st != CMHD_OK) return st;
   StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, t + RK_C[s] * dt)};
-  return hip_check(c, substage(c, s, src, dst, c->dF, a), "forward substage");
+  hipError_t e = driver_at(c, t + RK_C[s] * dt);
+  if (e == hipSuccess) e = substage(c, s, src, dst, c->dF, a);
+  return hip_check(c, e, "forward substage");
 }
 
 }  // namespace
@@ -607,6 +648,8 @@ cmhd_status cmhd_rk3_step_jvp(cmhd_ctx* c, double* x, double t, double dt, const
   if (!c || !x || !dx || !dy || !(dt > 0.0)) return CMHD_EINVAL;
   cmhd_status st = need_adj(c);
   if (st != CMHD_OK) return st;
+  if (duh && c->snap)
+    return fail(c, CMHD_EINVAL, "no driver perturbation with a snapshot pair as driver");
   const KParams& p = c->kp;
   hipStream_t s = c->stream;
   const size_t sbytes = state_elems(c->grid) * sizeof(double);
@@ -622,7 +665,8 @@ cmhd_status cmhd_rk3_step_jvp(cmhd_ctx* c, double* x, double t, double dt, const
   if (st != CMHD_OK) return st;
   for (int k = 0; k < 3; ++k) {
     const double rs = ramp(c, t + RK_C[k] * dt);
-    e = launch_fill_lin(p, X[k], DX, c->fft, s);
+    e = driver_at(c, t + RK_C[k] * dt);
+    if (e == hipSuccess) e = launch_fill_lin(p, X[k], DX, c->fft, s);
     if (e == hipSuccess) e = launch_point_q(p, X[k], c->Q, s);
     if (e == hipSuccess) e = launch_point_q(p, DX, c->Qb, s);
     if (e == hipSuccess) e = launch_point_jvp(p, c->Q, c->Qb, c->uh, c->ah, duh, rs, DR, s);
@@ -644,6 +688,8 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* c, double* x, double t, double dt, const
   if (!c || !x || !ybar || !xbar || !(dt > 0.0)) return CMHD_EINVAL;
   cmhd_status st = need_adj(c);
   if (st != CMHD_OK) return st;
+  if (uhbar && c->snap)
+    return fail(c, CMHD_EINVAL, "no driver cotangent with a snapshot pair as driver");
   const KParams& p = c->kp;
   hipStream_t s = c->stream;
   const size_t sbytes = state_elems(c->grid) * sizeof(double);
@@ -660,7 +706,8 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* c, double* x, double t, double dt, const
   if (e != hipSuccess) return hip_check(c, e, "vjp init");
   for (int k = 2; k >= 0; --k) {
     const double rs = ramp(c, t + RK_C[k] * dt);
-    e = launch_adj_combine(p, RK_ALPHA[k], RK_BETA[k], dt, c->XB, c->dFB, c->RB, s);
+    e = driver_at(c, t + RK_C[k] * dt);
+    if (e == hipSuccess) e = launch_adj_combine(p, RK_ALPHA[k], RK_BETA[k], dt, c->XB, c->dFB, c->RB, s);
     if (e == hipSuccess) e = launch_point_q(p, X[k], c->Q, s);
     if (e == hipSuccess) e = launch_point_vjp(p, c->Q, c->RB, c->uh, c->ah, rs, c->Qb, uhb, s);
     if (e == hipSuccess) e = launch_stencil_T(p, c->Qb, c->Gb, s);

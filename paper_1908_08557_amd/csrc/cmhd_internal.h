@@ -124,6 +124,10 @@ hipError_t launch_copy_state_entries(const KParams& p, const double* src, double
 hipError_t launch_bz_plane_vjp(const KParams& p, double zq, const double* bzbar, double* Xbar,
                                hipStream_t s);
 
+// uh = u0 + w (u1 - u0) over the two driver planes [2][ny][nx]
+hipError_t launch_driver_interp(const KParams& p, const double* u0, const double* u1, double w,
+                                double* uh, hipStream_t s);
+
 // 2-D FFT of nplanes complex planes [ny][nx] in place: sign -1 forward
 // (unnormalised), +1 inverse (unnormalised; the filters carry 1/(nx ny)).
 hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStream_t s);

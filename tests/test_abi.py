@@ -38,6 +38,9 @@ def test_struct_layout_matches_header():
     # cmhd_params: 8 + 3 + 1 + 9 doubles, int (padded), 2*16 doubles, 5 doubles
     assert ctypes.sizeof(cmhd.CmhdParams) == (21 * 8) + 8 + 32 * 8 + 5 * 8 + 5 * 8
     assert cmhd.CmhdParams.n_rad.offset == 21 * 8
+    # cmhd_gran_params: 2 ints, 11 doubles
+    assert ctypes.sizeof(cmhd.CmhdGranParams) == 8 + 11 * 8
+    assert cmhd.CmhdGranParams.f_rot.offset == 8 + 10 * 8
 
 
 def test_params_marshalling_roundtrip():
