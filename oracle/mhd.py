@@ -57,10 +57,36 @@ AX, AY, AZ, UX, UY, UZ, LNRHO, LNT = range(8)
 # grid helpers
 # ---------------------------------------------------------------------------
 
+class ZMetric:
+    """Metric of a non-uniform z grid z_k = z(zeta = k) (reading: z is a smooth
+    function of the plane index and the sixth-order stencils act in zeta):
+    d/dz = m1 d/dzeta, d2/dz2 = m1^2 d2/dzeta2 + m2 d/dzeta, with
+    m1 = 1/z', m2 = -z''/z'^3 and z', z'' the sixth-order differences of the
+    heights themselves, at the interior planes k = 0..nz-1."""
+
+    def __init__(self, z):
+        z = np.asarray(z, dtype=float)
+        zp = d1(z, 0, 1.0)
+        zpp = d2(z, 0, 1.0)
+        self.zp = zp
+        self.m1 = 1.0 / zp
+        self.m2 = -zpp / zp ** 3
+
+    def col(self, a, ndim):
+        return a.reshape((-1,) + (1,) * (ndim - 1))
+
+
+def stretched(grid):
+    return "z" in grid
+
+
 def spacings(grid):
-    """(dx, dy, dz).  Solar z is vertex-centred: z_0 = z0, z_{nz-1} = z1."""
+    """(dx, dy, dz).  Solar z is vertex-centred: z_0 = z0, z_{nz-1} = z1.  On
+    a non-uniform z grid the third entry is its ZMetric."""
     dx = grid["Lx"] / grid["nx"]
     dy = grid["Ly"] / grid["ny"]
+    if stretched(grid):
+        return dx, dy, ZMetric(grid["z"])
     if grid["zbc"] == "solar":
         dz = (grid["z1"] - grid["z0"]) / (grid["nz"] - 1)
     else:
@@ -70,6 +96,8 @@ def spacings(grid):
 
 def zk(grid):
     """Heights of the planes k = -3 .. nz+2."""
+    if stretched(grid):
+        return np.asarray(grid["z"], dtype=float)
     dz = spacings(grid)[2]
     return grid["z0"] + dz * np.arange(-NG, grid["nz"] + NG)
 
@@ -125,14 +153,20 @@ def _shift(f, ax, o):
 def d1(f, ax, h):
     """First derivative, 7-point, sixth order:
     [45 (f+1 - f-1) - 9 (f+2 - f-2) + (f+3 - f-3)] / (60 h).
-    The result is 6 points shorter along ax."""
+    The result is 6 points shorter along ax.  h may be a ZMetric (z axis)."""
+    if isinstance(h, ZMetric):
+        return h.col(h.m1, f.ndim) * d1(f, ax, 1.0)
     s = lambda o: _shift(f, ax, o)
     return (45.0 * (s(1) - s(-1)) - 9.0 * (s(2) - s(-2)) + (s(3) - s(-3))) / (60.0 * h)
 
 
 def d2(f, ax, h):
     """Second derivative, 7-point, sixth order:
-    [-490 f0 + 270 (f+1 + f-1) - 27 (f+2 + f-2) + 2 (f+3 + f-3)] / (180 h^2)."""
+    [-490 f0 + 270 (f+1 + f-1) - 27 (f+2 + f-2) + 2 (f+3 + f-3)] / (180 h^2).
+    h may be a ZMetric (z axis)."""
+    if isinstance(h, ZMetric):
+        return (h.col(h.m1 * h.m1, f.ndim) * d2(f, ax, 1.0)
+                + h.col(h.m2, f.ndim) * d1(f, ax, 1.0))
     s = lambda o: _shift(f, ax, o)
     return (-490.0 * s(0) + 270.0 * (s(1) + s(-1)) - 27.0 * (s(2) + s(-2))
             + 2.0 * (s(3) + s(-3))) / (180.0 * h * h)
@@ -229,7 +263,6 @@ def fill_ghosts(F, grid, par, lnrho0_z):
         F[:, nz + NG:] = F[:, NG:2 * NG]
         wrap_xy(F)
         return F
-    dx, dy, dz = spacings(grid)
     z = zk(grid)
     ny, nx = grid["ny"], grid["nx"]
     kabs = _kabs_rfft(nx, ny, grid["Lx"], grid["Ly"])
@@ -242,25 +275,36 @@ def fill_ghosts(F, grid, par, lnrho0_z):
         top = F[c, kt][I].copy()
         for j in (1, 2, 3):
             # inverted potential field below (contrast grows with depth, reduced by f_bot)
-            F[c, k0 - j][I] = kspace_filter(bot, np.exp(+par["f_bot"] * kabs * j * dz))
+            F[c, k0 - j][I] = kspace_filter(bot, np.exp(+par["f_bot"] * kabs * (z[k0] - z[k0 - j])))
             # potential field above, eq. (17)
-            F[c, kt + j][I] = kspace_filter(top, np.exp(-kabs * j * dz))
+            F[c, kt + j][I] = kspace_filter(top, np.exp(-kabs * (z[kt + j] - z[kt])))
     for j in (1, 2, 3):
         F[UZ, k0 - j][I] = -F[UZ, k0 + j][I]
         F[UZ, kt + j][I] = -F[UZ, kt - j][I]
         F[UX, kt + j][I] = F[UX, kt - j][I]
         F[UY, kt + j][I] = F[UY, kt - j][I]
         F[LNRHO, k0 - j][I] = lnrho0_z[k0 - j]
-    # lower T: hydrostatic recursion, eq. (8): ln p(-j) = ln p(-j+1) - dz g/(R T(-j+1))
+    # lower T: hydrostatic recursion, eq. (8):
+    # ln p(-j) = ln p(-j+1) - (z(-j+1) - z(-j)) g/(R T(-j+1))
     for j in (1, 2, 3):
         up = k0 - j + 1
         F[LNT, k0 - j][I] = (F[LNT, up][I] + F[LNRHO, up][I] - F[LNRHO, k0 - j][I]
-                             - dz * g / (R * np.exp(F[LNT, up][I])))
-    # upper T symmetric, eq. (11); upper rho hydrostatic mirror, eq. (13)
-    Ttop = np.exp(F[LNT, kt][I])
+                             - (z[up] - z[k0 - j]) * g / (R * np.exp(F[LNT, up][I])))
+    # upper T symmetric, eq. (11)
     for j in (1, 2, 3):
         F[LNT, kt + j][I] = F[LNT, kt - j][I]
-        F[LNRHO, kt + j][I] = F[LNRHO, kt - j][I] + g * (z[kt + j] - z[kt - j]) / (R * Ttop)
+    if not stretched(grid):
+        # upper rho hydrostatic mirror, eq. (13) (symmetric grid distances)
+        Ttop = np.exp(F[LNT, kt][I])
+        for j in (1, 2, 3):
+            F[LNRHO, kt + j][I] = F[LNRHO, kt - j][I] + g * (z[kt + j] - z[kt - j]) / (R * Ttop)
+    else:
+        # non-uniform z: the recursion of eq. (15), plane by plane upward
+        for j in (1, 2, 3):
+            Ta = np.exp(F[LNT, kt + j - 1][I])
+            Tb = np.exp(F[LNT, kt + j][I])
+            F[LNRHO, kt + j][I] = (F[LNRHO, kt + j - 1][I]
+                                   + (z[kt + j] - z[kt + j - 1]) * 2.0 * g / (R * (Tb + Ta)))
     wrap_xy(F)
     return F
 
@@ -561,8 +605,12 @@ def cfl_dt(F, grid, par):
     interior, from a ghost-filled state F (reading: the paper gives only the
     Courant number 0.4 and the Spitzer limitation)."""
     h = spacings(grid)
-    delta = min(h)
     nz = grid["nz"]
+    if stretched(grid):
+        # reading: the z spacing of plane k is z'(k); delta per plane
+        delta = np.minimum(min(h[0], h[1]), h[2].zp)[:, None, None]
+    else:
+        delta = min(h)
     gam, R, mu0 = par["gamma"], par["R"], par["mu0"]
     cv = R / (gam - 1.0)
     A = (F[AX], F[AY], F[AZ])
@@ -577,7 +625,10 @@ def cfl_dt(F, grid, par):
     B2 = B[0] ** 2 + B[1] ** 2 + B[2] ** 2
     cf = np.sqrt(gam * R * T + B2 / (mu0 * rho))
     speed = np.sqrt(ux ** 2 + uy ** 2 + uz ** 2) + cf
-    dt = par["c_adv"] * delta / np.max(speed)
+    if stretched(grid):
+        dt = par["c_adv"] * np.min(delta / speed)
+    else:
+        dt = par["c_adv"] * delta / np.max(speed)
 
     z = zk(grid)[NG:NG + nz]
     if grid["zbc"] == "solar":
@@ -593,7 +644,10 @@ def cfl_dt(F, grid, par):
         par["kappa0"] * T ** 2.5 / (rho * cv),
     ])
     dmax = np.max(D)
-    if dmax > 0:
+    if dmax > 0 and stretched(grid):
+        with np.errstate(divide="ignore"):
+            dt = min(dt, par["c_diff"] * float(np.min(delta * delta / D)))
+    elif dmax > 0:
         dt = min(dt, par["c_diff"] * delta * delta / dmax)
     qr = q_rad(rho, lT, par)
     if np.any(qr > 0):
@@ -614,9 +668,14 @@ def bz_at_height(F, grid, par, zq):
     """B_z = d_x A_y - d_y A_x (+ B_ext,z) on the horizontal plane at height
     zq, linear in z between the two enclosing grid planes."""
     h = spacings(grid)
-    kf = (zq - grid["z0"]) / h[2]
-    k0 = int(math.floor(kf))
-    a = kf - k0
+    if stretched(grid):
+        z = zk(grid)[NG:NG + grid["nz"]]
+        k0 = min(int(np.searchsorted(z, zq, side="right")) - 1, grid["nz"] - 2)
+        a = (zq - z[k0]) / (z[k0 + 1] - z[k0])
+    else:
+        kf = (zq - grid["z0"]) / h[2]
+        k0 = int(math.floor(kf))
+        a = kf - k0
     out = 0.0
     for k, wgt in ((k0, 1.0 - a), (k0 + 1, a)):
         if wgt == 0.0:

@@ -91,7 +91,10 @@ def grid_dict(nx, ny, nz, Lx, Ly, z0, z1, zbc):
 
 
 def z_coords(grid):
-    """z_k for k=-3..nz+2 (uniform; solar z is vertex-centred)."""
+    """z_k for k=-3..nz+2 and the spacing (uniform; solar z is
+    vertex-centred), or the given heights and None on a non-uniform grid."""
+    if "z" in grid:
+        return np.asarray(grid["z"], dtype=float), None
     nz = grid["nz"]
     if grid["zbc"] == "solar":
         dz = (grid["z1"] - grid["z0"]) / (nz - 1)
@@ -290,13 +293,30 @@ def enable_newton_cooling(w: "Workload", tau=0.5 * U_T):
     return w
 
 
-def stratified_box(nx, ny, nz, Lxy, z1, nbip, seed_bip, seed_u, name, t_ramp=None):
+def stretched_heights(nz, z0, d_lo, d_hi, k_c, width):
+    """Heights z_k, k = -3..nz+2, of a grid whose spacing rises smoothly from
+    d_lo to d_hi around plane index k_c (a tanh over `width` planes), in
+    closed form: dz/dk = d_lo + (d_hi - d_lo) (1 + tanh((k - k_c)/width)) / 2."""
+    k = np.arange(-NGHOST, nz + NGHOST, dtype=float)
+    lc = lambda x: np.logaddexp(x, -x) - math.log(2.0)     # ln cosh, overflow-free
+    return z0 + d_lo * k + 0.5 * (d_hi - d_lo) * (
+        k + width * (lc((k - k_c) / width) - lc(-k_c / width)))
+
+
+def stratified_box(nx, ny, nz, Lxy, z1, nbip, seed_bip, seed_u, name, t_ramp=None, z=None):
     """Stratified coronal box: tanh T0(z) 4e3 K -> 1e6 K at 2 Mm (width
     0.5 Mm), hydrostatic ln rho0 with rho(0) = 2.7e-4 kg/m^3, bottom B_z from
     seeded bipoles (peak 1 kG, sigma 2 Mm, separation 6 Mm) continued as a
     potential field, u = 0, driver u* solenoidal with rms 1 km/s and 1 Mm
     correlation length."""
+    if z is not None:
+        z1 = float(z[NGHOST + nz - 1])
     grid = grid_dict(nx, ny, nz, Lxy, Lxy, 0.0, z1, "solar")
+    if z is not None:
+        # non-uniform heights: z0, z1 are the bottom and top interior planes
+        grid.update(z=np.asarray(z, dtype=float), z0=float(z[NGHOST]),
+                    z1=float(z[NGHOST + nz - 1]))
+        z1 = grid["z1"]
     p = coronal_params(z1)
     if t_ramp is not None:
         p["t_ramp"] = t_ramp
@@ -313,6 +333,22 @@ def stratified_box(nx, ny, nz, Lxy, z1, nbip, seed_bip, seed_u, name, t_ramp=Non
     ah = state[0:2, NGHOST].copy()
     return Workload(name=name, grid=grid, params=p, lnrho0_z=lnrho0, lnT0_z=lnT0,
                     state=state, uh_target=uh, ah_target=ah, bz_bottom=bz)
+
+
+def small_stretched(nx=32, ny=32, nz=24, Lxy=20.0, nbip=2, seed_bip=2, seed_u=3, t_ramp=None):
+    """Reduced stratified box on a non-uniform z grid: spacing 0.25 Mm up to
+    ~2.5 Mm, rising to 1.5 Mm above (top ~22 Mm)."""
+    z = stretched_heights(nz, 0.0, 0.25, 1.5, 10.0, 4.0)
+    return stratified_box(nx, ny, nz, Lxy, None, nbip, seed_bip, seed_u,
+                          f"stretch{nx}x{ny}x{nz}", t_ramp=t_ramp, z=z)
+
+
+def strat512_stretched():
+    """The 512 x 512 x 256 box on the paper's kind of z grid: 100 km spacing
+    through the photosphere and chromosphere rising to 800 km in the corona
+    (top ~141 Mm)."""
+    z = stretched_heights(256, 0.0, 0.1, 0.8, 90.0, 20.0)
+    return stratified_box(512, 512, 256, 50.0, None, 8, 2, 3, "strat512_stretched", z=z)
 
 
 def strat64():
@@ -369,6 +405,7 @@ def small_stratified(nx=32, ny=32, nz=24, Lxy=20.0, z1=20.0, nbip=2, seed_bip=2,
 
 
 WORKLOADS = {
+    "strat512_stretched": strat512_stretched,
     "periodic16": lambda: periodic_box(16),
     "strat64": strat64,
     "strat512": strat512,

@@ -1,0 +1,191 @@
+"""Pins of the oracle on a non-uniform z grid: the metric derivatives against
+closed forms (exact when the heights and the function are polynomials of
+degree <= 6 in the plane index, sixth-order convergence otherwise), the
+reduction to the uniform stencils, an isothermal atmosphere at rest, the
+potential-field ghosts of a single mode at the actual ghost heights, the
+recursion of eq. (15) against the hydrostatic closed form, the per-plane CFL
+limit and the B_z plane between non-uniform planes."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mhd as O
+from paper_1908_08557_amd import workloads as W
+
+NG = O.NG
+
+
+def _column(values, ny=4, nx=4):
+    return np.asarray(values)[:, None, None] + np.zeros((1, ny, nx))
+
+
+def test_linear_map_reduces_to_the_uniform_stencils():
+    h = 0.37
+    z = 1.5 + h * np.arange(-NG, 20 + NG)
+    m = O.ZMetric(z)
+    assert np.allclose(m.m1, 1.0 / h, rtol=1e-14)
+    assert np.max(np.abs(m.m2)) < 1e-12
+    f = _column(np.sin(0.7 * z) + z ** 2)
+    assert np.allclose(O.d1(f, 0, m), O.d1(f, 0, h), rtol=1e-13, atol=1e-13)
+    assert np.allclose(O.d2(f, 0, m), O.d2(f, 0, h), rtol=1e-12, atol=1e-12)
+
+
+def test_exact_for_polynomials_in_the_plane_index():
+    # z(zeta) = 2 + 0.3 zeta + 0.004 zeta^2 (monotone on the range), f = zeta^3:
+    # df/dz = 3 zeta^2 / z', d2f/dz2 = (6 zeta z' - 3 zeta^2 z'') / z'^3
+    zeta = np.arange(-NG, 30 + NG, dtype=float)
+    z = 2.0 + 0.3 * zeta + 0.004 * zeta ** 2
+    m = O.ZMetric(z)
+    zi = zeta[NG:-NG]
+    zp, zpp = 0.3 + 0.008 * zi, 0.008
+    assert np.allclose(m.zp, zp, rtol=1e-14)
+    f = _column(zeta ** 3)
+    d1 = O.d1(f, 0, m)[:, 0, 0]
+    d2 = O.d2(f, 0, m)[:, 0, 0]
+    assert np.allclose(d1, 3 * zi ** 2 / zp, rtol=1e-12, atol=1e-12)
+    assert np.allclose(d2, (6 * zi * zp - 3 * zi ** 2 * zpp) / zp ** 3, rtol=1e-11, atol=1e-11)
+
+
+def test_sixth_order_convergence_on_a_tanh_stretched_grid():
+    errs = []
+    for n in (32, 64):
+        z = W.stretched_heights(n, 0.0, 0.5 * 32 / n, 2.0 * 32 / n, 0.4 * n, 0.12 * n)
+        m = O.ZMetric(z)
+        f = _column(np.sin(0.35 * z))
+        zi = z[NG:-NG]
+        e1 = np.max(np.abs(O.d1(f, 0, m)[:, 0, 0] - 0.35 * np.cos(0.35 * zi)))
+        e2 = np.max(np.abs(O.d2(f, 0, m)[:, 0, 0] + 0.35 ** 2 * np.sin(0.35 * zi)))
+        errs.append((e1, e2))
+    assert errs[0][0] / errs[1][0] > 40 and errs[0][1] / errs[1][1] > 40
+
+
+def _isothermal_stretched(nz=16):
+    # heights quadratic in the index: ln rho linear in z is then a polynomial
+    # of degree 2 in the index and the hydrostatic balance is exact
+    w = W.small_stretched(8, 8, nz, Lxy=8.0, nbip=1)
+    zeta = np.arange(-NG, nz + NG, dtype=float)
+    z = 0.25 * zeta + 0.02 * zeta ** 2
+    g = w.grid
+    g.update(z=z, z0=0.0, z1=float(z[NG + nz - 1]))
+    p = W.base_params()
+    T0 = 1e4
+    p.update(R=w.params["R"], g_z=w.params["g_z"], kappa0=0.0, eta=0.0, nu=0.0,
+             z_s=z[NG + nz - 1] - 1.0, z_t=z[NG + nz - 1], tau_u=0.0, tau_A=0.0)
+    w.params = p
+    lnr = 2.0 + p["g_z"] * z / (p["R"] * T0)
+    w.lnrho0_z = lnr
+    w.lnT0_z = np.full_like(z, math.log(T0))
+    w.state[:] = 0.0
+    w.state[6] = lnr[:, None, None]
+    w.state[7] = math.log(T0)
+    w.uh_target = np.zeros((2, 8, 8))
+    w.ah_target = np.zeros((2, 8, 8))
+    return w
+
+
+def test_isothermal_atmosphere_at_rest():
+    w = _isothermal_stretched()
+    F = O.from_compact(w.state)
+    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
+    # the ghost rules continue the profile: eq. (8) keeps T, eq. (15) the
+    # exponential density
+    assert np.allclose(F[O.LNT], math.log(1e4), rtol=0, atol=1e-13)
+    assert np.allclose(F[O.LNRHO][:, 3, 3], w.lnrho0_z, rtol=0, atol=1e-12)
+    cs = math.sqrt(w.params["gamma"] * w.params["R"] * 1e4)
+    dt = O.cfl_dt(F, w.grid, w.params)
+    drv = dict(uh=w.uh_target, ah=w.ah_target)
+    F2, _ = O.run(F, 0.0, dt, 20, w.grid, w.params, w.lnrho0_z, drv)
+    assert np.max(np.abs(O.interior(F2[O.UZ]))) < 1e-11 * cs
+
+
+def test_potential_field_ghosts_at_the_ghost_heights():
+    w = W.small_stretched(16, 16, 12, Lxy=8.0, nbip=1)
+    g, p = w.grid, w.params
+    z = O.zk(g)
+    F = O.from_compact(np.zeros_like(w.state))
+    F[O.LNT] = math.log(1e4)
+    k = 2 * np.pi * 3 / 8.0
+    X = np.arange(16) * 0.5
+    mode = np.sin(k * X)[None, :] + np.zeros((16, 1))
+    k0, kt = NG, NG + 11
+    F[O.AY, k0, NG:-NG, NG:-NG] = mode
+    F[O.AY, kt, NG:-NG, NG:-NG] = mode
+    O.fill_ghosts(F, g, p, w.lnrho0_z)
+    for j in (1, 2, 3):
+        up = F[O.AY, kt + j, NG:-NG, NG:-NG]
+        dn = F[O.AY, k0 - j, NG:-NG, NG:-NG]
+        assert np.allclose(up, mode * math.exp(-k * (z[kt + j] - z[kt])), atol=1e-14)
+        assert np.allclose(dn, mode * math.exp(p["f_bot"] * k * (z[k0] - z[k0 - j])), atol=1e-13)
+    assert z[kt + 3] - z[kt + 2] != z[kt + 1] - z[kt]      # really non-uniform there
+
+
+def test_eq15_recursion_matches_hydrostatic_closed_form_for_linear_T():
+    # T linear in z across the top ghosts, g constant: the exact hydrostatic
+    # density ln rho(z) = ln rho_top + g/(R b) ln(T(z)/T_top), T = T_top + b (z - z_top);
+    # the recursion of eq. (15) (trapezoid in 1/T over three ghost
+    # intervals) approaches it as the spacing cubed
+    errs = []
+    for scale in (1.0, 0.5):
+        w = W.small_stretched(8, 8, 12, Lxy=8.0, nbip=1)
+        zeta = np.arange(-NG, 12 + NG, dtype=float)
+        z = scale * (0.25 * zeta + 0.02 * zeta ** 2)
+        g, p = w.grid, w.params
+        g.update(z=z, z0=0.0, z1=float(z[NG + 11]))
+        kt = NG + 11
+        F = O.from_compact(np.zeros_like(w.state))
+        b = -2e3
+        Ttop = 2e4
+        T = Ttop + b * (z - z[kt])
+        # the symmetric rule of eq. (11) mirrors T: choose a T symmetric
+        # about the top plane by construction
+        Tm = Ttop + b * np.abs(z - z[kt])
+        for kk in range(F.shape[1]):
+            F[O.LNT, kk] = math.log(Tm[kk]) if kk <= kt else F[O.LNT, kk]
+        F[O.LNRHO] = w.lnrho0_z[:, None, None]     # a consistent lower column
+        F[O.LNRHO, kt] = 1.0
+        O.fill_ghosts(F, g, p, w.lnrho0_z)
+        got = F[O.LNRHO, kt + 3, NG, NG]
+        Tg = np.exp(F[O.LNT, kt:kt + 4, NG, NG])
+        zz = z[kt:kt + 4]
+        # exact integral of g/(R T) for T piecewise linear between the planes
+        exact = 1.0
+        for i in range(3):
+            bb = (Tg[i + 1] - Tg[i]) / (zz[i + 1] - zz[i])
+            exact += p["g_z"] / (p["R"] * bb) * math.log(Tg[i + 1] / Tg[i])
+        errs.append(abs(got - exact))
+    assert errs[0] > 0 and 6.0 < errs[0] / errs[1] < 10.0
+
+
+def test_cfl_uses_the_local_spacing():
+    w = _isothermal_stretched()
+    F = O.from_compact(w.state)
+    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
+    cs = math.sqrt(w.params["gamma"] * w.params["R"] * 1e4)
+    m = O.ZMetric(w.grid["z"])
+    dmin = min(8.0 / 8, float(np.min(m.zp)))
+    dt = O.cfl_dt(F, w.grid, w.params)
+    assert dt == pytest.approx(w.params["c_adv"] * dmin / cs, rel=1e-14)
+    # the limit comes from the finest plane, not from dx or a mean spacing
+    assert float(np.min(m.zp)) < 1.0 and float(np.max(m.zp)) > 3 * float(np.min(m.zp))
+
+
+def test_bz_plane_between_non_uniform_planes():
+    w = W.small_stretched(16, 16, 12, Lxy=8.0, nbip=1)
+    g, p = w.grid, w.params
+    p["Bext"] = [0.0, 0.0, 0.0]
+    z = O.zk(g)
+    F = O.from_compact(np.zeros_like(w.state))
+    X = np.arange(16) * 0.5
+    kx = 2 * np.pi / 8.0
+    for kk in range(F.shape[1]):
+        # A_y = sin(kx x) (1 + z^2): B_z = kx cos(kx x) (1 + z^2)
+        F[O.AY, kk, NG:-NG, NG:-NG] = np.sin(kx * X)[None, :] * (1 + z[kk] ** 2)
+    O.wrap_xy(F)
+    zq = 0.3 * z[NG + 4] + 0.7 * z[NG + 5]
+    bz = O.bz_at_height(F, g, p, zq)
+    lin = 0.3 * (1 + z[NG + 4] ** 2) + 0.7 * (1 + z[NG + 5] ** 2)
+    d1x = O.d1(np.sin(kx * np.arange(-NG, 16 + NG) * 0.5), 0, 0.5)
+    assert np.allclose(bz[0], d1x * lin, rtol=1e-13, atol=1e-13)
+    assert np.allclose(O.bz_at_height(F, g, p, z[NG + 4])[0], d1x * (1 + z[NG + 4] ** 2),
+                       rtol=1e-14)
