@@ -105,6 +105,7 @@ def test_potential_field_ghosts_at_the_ghost_heights():
     z = O.zk(g)
     F = O.from_compact(np.zeros_like(w.state))
     F[O.LNT] = math.log(1e4)
+    F[O.LNRHO] = w.lnrho0_z[:, None, None]
     k = 2 * np.pi * 3 / 8.0
     X = np.arange(16) * 0.5
     mode = np.sin(k * X)[None, :] + np.zeros((16, 1))
