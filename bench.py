@@ -12,9 +12,9 @@ re-seeded every 10 steps (device-resident targets, set with cmhd_set_driver).
 
 Prints one JSON line: the FP64 throughput (zone-updates/s) as `value`, the
 FP32-split form beside it, the HBM roofline of the fused kernel from HIP
-events around its launches, the granulation driver's cost per snapshot on the
-same photospheric plane (outside the timed steps), and the CPU oracle timed on
-a bounded sample.
+events around its launches, the same box on a non-uniform z grid (FP64), the
+granulation driver's cost per snapshot on the same photospheric plane (outside
+the timed steps), and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32_split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-driver", action="store_true", help="skip the granulation-driver timing")
+    ap.add_argument("--no-stretched", action="store_true",
+                    help="skip the same box on the non-uniform z grid")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -253,6 +255,19 @@ def main():
         out["roofline"]["traffic_source"] = tr["profile"]
         out["roofline"]["valu_busy_pct"] = tr["valu_busy_pct_fused"]
     out["finite"] = all(v["finite"] for v in res.values())
+    if not args.no_stretched and w.name == "strat512":
+        # the same box on the paper's kind of z grid (100 km -> 800 km), FP64
+        log("[bench] strat512_stretched fp64")
+        ws = W.strat512_stretched()
+        rs = run_gpu(ws, "fp64", max(args.steps // 2, 1), args.warmup,
+                     [torch.as_tensor(W.driver_reseed(ws, 100 + k), device="cuda")
+                      for k in range(2)])
+        log(f"[bench] strat512_stretched: {rs}")
+        out["stretched_z"] = {"workload": "strat512_stretched: 512x512x256, z spacing 0.1 -> "
+                                          "0.8 Mm (top 141 Mm)",
+                              "value": rs["value"], "ms_per_step": rs["ms_per_step"],
+                              "substage_ms": rs["substage_ms"], "roofline_frac": rs["frac"],
+                              "steps": max(args.steps // 2, 1), "finite": rs["finite"]}
     if not args.no_driver and g["zbc"] == "solar":
         log("[bench] granulation driver")
         out["driver"] = driver_bench(w, r["dt"], r["ms_per_step"])

@@ -141,6 +141,24 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
                            const double* lnrho0_z, const double* lnT0_z, void* stream,
                            cmhd_ctx** out);
 
+/* As cmhd_init_grid on a non-uniform z grid (Introduction: the production
+ * grid refines from ~800 km in the corona to ~100 km in the lower
+ * atmosphere).  z: host [nz+6], the heights z_k of the planes k = -3..nz+2,
+ * strictly increasing (copied); grid.z0 and grid.z1 are ignored (the
+ * interior runs from z_0 to z_{nz-1}); solar boundaries only.  The sixth-order
+ * stencils act in the plane index k and are scaled by the metric of the
+ * mapping: d/dz = (1/z') d/dk, d2/dz2 = (1/z'^2) d2/dk2 - (z''/z'^3) d/dk,
+ * with z' and z'' the same stencils applied to the heights.  The ghost rules
+ * use the actual heights: eq. (8) below and the potential fields at the
+ * ghost heights; the upper density follows the recursion of eq. (15) (the
+ * mirror form of eq. 13 needs symmetric grid distances).  The time step uses
+ * each plane's own spacing min(dx, dy, z'_k).  z = NULL is cmhd_init_grid.
+ * The tangent and adjoint steps (cmhd_rk3_step_jvp/vjp, cmhd_bz_plane_vjp)
+ * return CMHD_EINVAL on a non-uniform grid. */
+cmhd_status cmhd_init_grid_z(const cmhd_grid* grid, const cmhd_params* params, const double* z,
+                             const double* lnrho0_z, const double* lnT0_z, void* stream,
+                             cmhd_ctx** out);
+
 /* Number of doubles of one state buffer: 8*(nz+6)*ny*nx. */
 size_t cmhd_state_elems(const cmhd_ctx* ctx);
 

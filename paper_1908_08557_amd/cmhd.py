@@ -72,6 +72,9 @@ def load():
     sig = {
         "cmhd_init_grid": (I, [ctypes.POINTER(CmhdGrid), ctypes.POINTER(CmhdParams),
                                ctypes.POINTER(D), ctypes.POINTER(D), P, ctypes.POINTER(P)]),
+        "cmhd_init_grid_z": (I, [ctypes.POINTER(CmhdGrid), ctypes.POINTER(CmhdParams),
+                                 ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), P,
+                                 ctypes.POINTER(P)]),
         "cmhd_state_elems": (S, [P]),
         "cmhd_workspace_bytes": (S, [P]),
         "cmhd_bind_workspace": (I, [P, P, S]),
@@ -114,7 +117,7 @@ def load():
 
 def exported_symbols():
     """Names the binding expects the library to export."""
-    return ["cmhd_init_grid", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
+    return ["cmhd_init_grid", "cmhd_init_grid_z", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
             "cmhd_set_stream", "cmhd_set_driver", "cmhd_set_driver_snapshots",
             "cmhd_fill_ghosts", "cmhd_rk3_step",
             "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_bz_plane", "cmhd_check_finite",
@@ -182,8 +185,13 @@ class Solver:
         dptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        rc = self.lib.cmhd_init_grid(ctypes.byref(self._g), ctypes.byref(self._p), dptr(lr),
-                                     dptr(lt), ctypes.c_void_p(stream), ctypes.byref(ctx))
+        zz = None
+        if "z" in grid:
+            zz = np.ascontiguousarray(np.asarray(grid["z"], dtype=np.float64))
+        self._z = zz
+        rc = self.lib.cmhd_init_grid_z(ctypes.byref(self._g), ctypes.byref(self._p), dptr(zz),
+                                       dptr(lr), dptr(lt), ctypes.c_void_p(stream),
+                                       ctypes.byref(ctx))
         if rc != CMHD_OK:
             raise CmhdError(rc, "cmhd_init_grid failed (see stderr)")
         self.ctx = ctx

@@ -70,20 +70,30 @@ __global__ void k_fill_solar_columns(const KParams p, double* __restrict__ f) {
       uy[(kt + j) * sp] = uy[(kt - j) * sp];
       lr[(kb - j) * sp] = p.lnrho0_bot[NG - j];
     }
-    // hydrostatic lower temperature ghosts, recursive downward
+    // hydrostatic lower temperature ghosts, recursive downward (eq. 8)
 #pragma unroll
     for (int j = 1; j <= NG; ++j) {
       const int up = kb - j + 1;
       const double Tup = exp(lT[up * sp]);
       lT[(kb - j) * sp] =
-          lT[up * sp] + lr[up * sp] - lr[(kb - j) * sp] - p.dz * p.g_z / (p.R * Tup);
+          lT[up * sp] + lr[up * sp] - lr[(kb - j) * sp] - p.dz_lo[j - 1] * p.g_z / (p.R * Tup);
     }
-    // symmetric temperature and hydrostatic density above
-    const double Ttop = exp(lT[kt * sp]);
+    // symmetric temperature above (eq. 11)
 #pragma unroll
-    for (int j = 1; j <= NG; ++j) {
-      lT[(kt + j) * sp] = lT[(kt - j) * sp];
-      lr[(kt + j) * sp] = lr[(kt - j) * sp] + p.g_z * (2.0 * j * p.dz) / (p.R * Ttop);
+    for (int j = 1; j <= NG; ++j) lT[(kt + j) * sp] = lT[(kt - j) * sp];
+    if (!p.stretched) {
+      // hydrostatic mirror density (eq. 13; symmetric grid distances)
+      const double Ttop = exp(lT[kt * sp]);
+#pragma unroll
+      for (int j = 1; j <= NG; ++j)
+        lr[(kt + j) * sp] = lr[(kt - j) * sp] + p.g_z * (2.0 * j * p.dz) / (p.R * Ttop);
+    } else {
+      // non-uniform grid: the recursion of eq. (15), upward
+#pragma unroll
+      for (int j = 1; j <= NG; ++j) {
+        const double Ta = exp(lT[(kt + j - 1) * sp]), Tb = exp(lT[(kt + j) * sp]);
+        lr[(kt + j) * sp] = lr[(kt + j - 1) * sp] + p.dz_hi[j - 1] * 2.0 * p.g_z / (p.R * (Tb + Ta));
+      }
     }
   }
 }
@@ -159,8 +169,9 @@ __global__ void k_pack_boundary_planes(const KParams p, const double* __restrict
   }
 }
 
-// T[q*3 + j-1] = S[q] * exp(-|k| d_qj) / (nx ny), d = -f_bot j dz below
-// (contrast grows with depth, Sect. 2.4) and d = j dz above (eq. 17)
+// T[q*3 + j-1] = S[q] * exp(-|k| d_qj) / (nx ny), d = -f_bot (z(0) - z(-j))
+// below (contrast grows with depth, Sect. 2.4) and d = z(nz-1+j) - z(nz-1)
+// above (eq. 17)
 __global__ void k_pf_filter(const KParams p, const double2* __restrict__ S,
                             double2* __restrict__ T) {
   const long long sp = p.splane;
@@ -172,10 +183,10 @@ __global__ void k_pf_filter(const KParams p, const double2* __restrict__ S,
     const int iy = int(col / p.nx), ix = int(col - (long long)iy * p.nx);
     const double k = kabs(p, ix, iy);
     const double2 v = S[i];
-    const double per = q < 2 ? -p.f_bot * p.dz : p.dz;
+    const double* dist = p.pf_dist[q < 2 ? 0 : 1];
 #pragma unroll
     for (int j = 1; j <= NG; ++j) {
-      const double fac = exp(-k * (j * per)) * inv_n;
+      const double fac = exp(-k * dist[j - 1]) * inv_n;
       T[(q * NG + j - 1) * sp + col] = make_double2(v.x * fac, v.y * fac);
     }
   }
@@ -297,8 +308,9 @@ __global__ void k_cfl(const KParams p, const double* __restrict__ f,
     const long long o = (long long)kz * p.splane + col;
     const double dAz_dy = d1xy(p, f, AZ, kz, col, 1), dAz_dx = d1xy(p, f, AZ, kz, col, 0);
     const double dAy_dx = d1xy(p, f, AY, kz, col, 0), dAx_dy = d1xy(p, f, AX, kz, col, 1);
-    const double dAy_dz = d1col(f + AY * p.sfield + o, p.splane) * p.i60dz;
-    const double dAx_dz = d1col(f + AX * p.sfield + o, p.splane) * p.i60dz;
+    const double mz = p.stretched ? p.ztab[zt_c1(p) + k] : p.i60dz;
+    const double dAy_dz = d1col(f + AY * p.sfield + o, p.splane) * mz;
+    const double dAx_dz = d1col(f + AX * p.sfield + o, p.splane) * mz;
     const double Bx = dAz_dy - dAy_dz + p.Bext[0];
     const double By = dAx_dz - dAz_dx + p.Bext[1];
     const double Bz = dAy_dx - dAx_dy + p.Bext[2];
@@ -307,10 +319,10 @@ __global__ void k_cfl(const KParams p, const double* __restrict__ f,
     const double rho = exp(lr), T = exp(lT);
     const double B2 = Bx * Bx + By * By + Bz * Bz;
     const double cf = sqrt(p.gamma * p.R * T + B2 / (p.mu0 * rho));
-    const double spd = sqrt(ux * ux + uy * uy + uz * uz) + cf;
+    double spd = sqrt(ux * ux + uy * uy + uz * uz) + cf;
     double w = 0.0;
     if (p.solar) {
-      const double z = p.z0 + k * p.dz;
+      const double z = zk(p, k);
       double s = (z - p.z_s) / (p.z_t - p.z_s);
       s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
       w = s * s * (3.0 - 2.0 * s);
@@ -320,6 +332,12 @@ __global__ void k_cfl(const KParams p, const double* __restrict__ f,
     D = fmax(D, p.D_rho + p.chi_rho * w);
     D = fmax(D, p.chi_s * w);
     D = fmax(D, p.kappa0 * exp(2.5 * lT) / (rho * p.cv));
+    if (p.stretched) {
+      // non-uniform grid: rates per unit of the plane's own spacing
+      const double dl = fmin(p.dxy_min, p.ztab[zt_zp(p) + k]);
+      spd = spd / dl;
+      D = D / (dl * dl);
+    }
     double rate = 0.0;
     if (p.n_rad > 0 && lT > p.lnT_rad_lo) {
       int seg = 0;
@@ -476,6 +494,12 @@ hipError_t launch_cfl_max(const KParams& p, const double* f, unsigned long long*
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out3, 3);
   hipLaunchKernelGGL(k_cfl, dim3(grid_for((long long)p.nz * p.splane)), dim3(256), 0, s, p, f,
                      out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_bz_plane_k(const KParams& p, const double* f, int k0, double a, double* dst,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_bz_plane, dim3(grid_for(p.splane)), dim3(256), 0, s, p, f, k0, a, dst);
   return hipGetLastError();
 }
 

@@ -33,6 +33,9 @@ struct cmhd_ctx {
   void* dz = nullptr;     // z derivatives of the substage input [16][nz][ny][nx]
   std::vector<double> nc_host;   // initial [ln rho0 | ln T0] profiles (Newtonian cooling)
   double* nc_dev = nullptr;      // their device copy in the workspace
+  std::vector<double> z_host;    // plane heights z_k, k = -3..nz+2
+  std::vector<double> zt_host;   // the z table of KParams::ztab (non-uniform grids)
+  double* zt_dev = nullptr;
   // second stream for the z-derivative pass of the pipelined substage, and
   // the events that order it against the caller's stream (created at init)
   hipStream_t zs = nullptr;
@@ -90,7 +93,53 @@ size_t ws_layout(const cmhd_ctx* c, size_t off[16]) {
   off[8] = o; o += align256(2 * size_t(c->kp.nc_n) * sizeof(double));   // ln rho0, ln T0
   off[9] = o; o += align256(2 * plane * sizeof(double));         // driver snapshot 0
   off[10] = o; o += align256(2 * plane * sizeof(double));        // driver snapshot 1
+  off[11] = o; o += align256(size_t(zt_size(c->kp)) * sizeof(double));  // z table
   return o;
+}
+
+// heights, metric and ghost distances of the z grid.  zin: the caller's
+// heights (non-uniform grid) or NULL (uniform: z0 + k dz)
+void fill_zgrid(cmhd_ctx* c, const double* zin) {
+  KParams& p = c->kp;
+  const int nz = p.nz, n = nz + 2 * NG;
+  c->z_host.resize(n);
+  for (int i = 0; i < n; ++i) c->z_host[i] = zin ? zin[i] : p.z0 + (i - NG) * p.dz;
+  const double* z = c->z_host.data();
+  p.stretched = zin != nullptr;
+  p.dxy_min = std::fmin(p.dx, p.dy);
+  c->zt_host.assign(size_t(zt_size(p)), 0.0);
+  for (int i = 0; i < n; ++i) c->zt_host[i] = z[i];
+  if (p.stretched) {
+    p.z0 = z[NG];
+    // z' and z'' at the interior planes from the sixth-order stencils in the
+    // plane index applied to the heights
+    for (int k = 0; k < nz; ++k) {
+      const double* w = z + k + NG;
+      const double zp = (45.0 * (w[1] - w[-1]) - 9.0 * (w[2] - w[-2]) + (w[3] - w[-3])) / 60.0;
+      const double zpp =
+          (-490.0 * w[0] + 270.0 * (w[1] + w[-1]) - 27.0 * (w[2] + w[-2]) + 2.0 * (w[3] + w[-3])) /
+          180.0;
+      c->zt_host[zt_c1(p) + k] = 1.0 / (60.0 * zp);
+      c->zt_host[zt_c2(p) + k] = 1.0 / (180.0 * zp * zp);
+      c->zt_host[zt_c3(p) + k] = -zpp / (60.0 * zp * zp * zp);
+      c->zt_host[zt_zp(p) + k] = zp;
+    }
+  }
+  const int kb = NG, kt = NG + nz - 1;
+  for (int j = 1; j <= NG; ++j) {
+    if (p.stretched) {
+      p.dz_lo[j - 1] = z[kb - j + 1] - z[kb - j];
+      p.dz_hi[j - 1] = z[kt + j] - z[kt + j - 1];
+      p.pf_dist[0][j - 1] = -p.f_bot * (z[kb] - z[kb - j]);
+      p.pf_dist[1][j - 1] = z[kt + j] - z[kt];
+    } else {
+      p.dz_lo[j - 1] = p.dz;
+      p.dz_hi[j - 1] = p.dz;
+      p.pf_dist[0][j - 1] = j * (-p.f_bot * p.dz);
+      p.pf_dist[1][j - 1] = j * p.dz;
+    }
+  }
+  p.ztab = nullptr;   // set when the workspace is bound
 }
 
 void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
@@ -200,9 +249,16 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
   double m[3];
   std::memcpy(m, h, sizeof(m));
   const KParams& p = c->kp;
-  double delta = std::fmin(p.dx, std::fmin(p.dy, p.dz));
-  double dt = p.c_adv * delta / m[0];
-  if (m[1] > 0.0) dt = std::fmin(dt, p.c_diff * delta * delta / m[1]);
+  double dt;
+  if (p.stretched) {
+    // the kernel reduced speed / spacing and D / spacing^2 per plane
+    dt = p.c_adv / m[0];
+    if (m[1] > 0.0) dt = std::fmin(dt, p.c_diff / m[1]);
+  } else {
+    const double delta = std::fmin(p.dx, std::fmin(p.dy, p.dz));
+    dt = p.c_adv * delta / m[0];
+    if (m[1] > 0.0) dt = std::fmin(dt, p.c_diff * delta * delta / m[1]);
+  }
   if (m[2] > 0.0) dt = std::fmin(dt, p.c_adv / m[2]);
   double tau = p.solar ? std::fmax(p.tau_u, p.tau_A) : 0.0;
   tau = std::fmax(tau, p.nc_tau);
@@ -218,9 +274,9 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
 
 extern "C" {
 
-cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
-                           const double* lnrho0_z, const double* lnT0_z, void* stream,
-                           cmhd_ctx** out) {
+cmhd_status cmhd_init_grid_z(const cmhd_grid* grid, const cmhd_params* params, const double* z,
+                             const double* lnrho0_z, const double* lnT0_z, void* stream,
+                             cmhd_ctx** out) {
   if (!out) return CMHD_EINVAL;
   *out = nullptr;
   if (!grid || !params) return CMHD_EINVAL;
@@ -236,7 +292,7 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
     why = "zbc must be CMHD_ZBC_PERIODIC or CMHD_ZBC_SOLAR";
   else if (g.prec != CMHD_FP64 && g.prec != CMHD_FP32_SPLIT)
     why = "prec must be CMHD_FP64 or CMHD_FP32_SPLIT";
-  else if (!(g.Lx > 0) || !(g.Ly > 0) || !(g.z1 > g.z0))
+  else if (!(g.Lx > 0) || !(g.Ly > 0) || (!z && !(g.z1 > g.z0)))
     why = "domain lengths must be positive";
   else if (!(q.gamma > 1.0) || !(q.R > 0) || !(q.mu0 > 0))
     why = "gamma > 1, R > 0 and mu0 > 0 are required";
@@ -264,6 +320,10 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
   for (int i = 0; why.empty() && q.nc_tau > 0.0 && i + 1 < g.nz + 2 * NG; ++i)
     if (!(lnrho0_z[i + 1] < lnrho0_z[i]))
       why = "the Newtonian cooling needs ln rho0(z) to decrease strictly with height";
+  if (why.empty() && z && !solar) why = "a non-uniform z grid needs the solar boundaries";
+  for (int i = 0; why.empty() && z && i < g.nz + 2 * NG; ++i)
+    if (!std::isfinite(z[i]) || (i > 0 && !(z[i] > z[i - 1])))
+      why = "the heights z_k must be finite and increase strictly";
   if (!why.empty()) {
     std::fprintf(stderr, "cmhd_init_grid: %s\n", why.c_str());
     return CMHD_EINVAL;
@@ -284,6 +344,7 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
   c->par = q;
   c->stream = (hipStream_t)stream;
   fill_kparams(c, lnrho0_z);
+  fill_zgrid(c, z);
   {
     const int n = g.nz + 2 * NG;
     c->nc_host.assign(2 * size_t(n), 0.0);
@@ -305,6 +366,12 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
   }
   *out = c;
   return CMHD_OK;
+}
+
+cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
+                           const double* lnrho0_z, const double* lnT0_z, void* stream,
+                           cmhd_ctx** out) {
+  return cmhd_init_grid_z(grid, params, nullptr, lnrho0_z, lnT0_z, stream, out);
 }
 
 size_t cmhd_state_elems(const cmhd_ctx* c) { return c ? state_elems(c->grid) : 0; }
@@ -339,6 +406,8 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->u0 = reinterpret_cast<double*>(c->ws + off[9]);
   c->u1 = reinterpret_cast<double*>(c->ws + off[10]);
   c->snap = false;
+  c->zt_dev = reinterpret_cast<double*>(c->ws + off[11]);
+  c->kp.ztab = c->zt_dev;
   c->kp.nc_tab = c->nc_dev;
   // driver targets start at zero; the stage buffers are fully written before use
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
@@ -347,6 +416,11 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->nc_dev, c->nc_host.data(), c->nc_host.size() * sizeof(double),
                        hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->zt_dev, c->zt_host.data(), c->zt_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
+  // the tables are read from host vectors that outlive the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return hip_check(c, e, "workspace clear");
 }
 
@@ -565,9 +639,17 @@ cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, dou
 cmhd_status cmhd_bz_plane(cmhd_ctx* c, const double* state, double z, double* dst) {
   if (!c || !state || !dst) return CMHD_EINVAL;
   const KParams& p = c->kp;
-  if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
-    return fail(c, CMHD_EINVAL, "z outside the interior");
-  return hip_check(c, launch_bz_plane(p, state, z, dst, c->stream), "bz_plane launch");
+  if (!p.stretched) {
+    if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
+      return fail(c, CMHD_EINVAL, "z outside the interior");
+    return hip_check(c, launch_bz_plane(p, state, z, dst, c->stream), "bz_plane launch");
+  }
+  const double* zi = c->z_host.data() + NG;
+  if (!(z >= zi[0]) || !(z <= zi[p.nz - 1])) return fail(c, CMHD_EINVAL, "z outside the interior");
+  int k0 = int(std::upper_bound(zi, zi + p.nz, z) - zi) - 1;
+  k0 = std::min(k0, p.nz - 2);
+  const double a = (z - zi[k0]) / (zi[k0 + 1] - zi[k0]);
+  return hip_check(c, launch_bz_plane_k(p, state, k0, a, dst, c->stream), "bz_plane launch");
 }
 
 cmhd_status cmhd_check_finite(cmhd_ctx* c, const double* state) {
@@ -603,6 +685,8 @@ size_t adj_layout(const cmhd_ctx* c, size_t off[8]) {
 cmhd_status need_adj(cmhd_ctx* c) {
   cmhd_status st = need_ws(c);
   if (st != CMHD_OK) return st;
+  if (c->kp.stretched)
+    return fail(c, CMHD_EINVAL, "the tangent and adjoint steps support uniform z grids only");
   if (!c->aws) return fail(c, CMHD_ESTATE, "no adjoint workspace bound");
   return CMHD_OK;
 }
@@ -725,6 +809,8 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* c, double* x, double t, double dt, const
 cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* c, double z, const double* bzbar, double* xbar) {
   if (!c || !bzbar || !xbar) return CMHD_EINVAL;
   const KParams& p = c->kp;
+  if (p.stretched)
+    return fail(c, CMHD_EINVAL, "the adjoint supports uniform z grids only");
   if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
     return fail(c, CMHD_EINVAL, "z outside the interior");
   return hip_check(c, launch_bz_plane_vjp(p, z, bzbar, xbar, c->stream), "bz_plane_vjp launch");

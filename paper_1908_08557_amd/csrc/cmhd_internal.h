@@ -48,7 +48,35 @@ struct KParams {
   double nc_tau, nc_dlr0, nc_dlrw, nc_z0, nc_zw, nc_lnrho_phot;
   int nc_n;
   const double* nc_tab;
+  // non-uniform z grid (stretched != 0; uniform grids use z0 + k dz):
+  // spacings of the ghost planes, the distances of the potential-field
+  // filters, min(dx, dy), and the device table ztab = [z_k (nz+6) |
+  // c1 = 1/(60 z') | c2 = 1/(180 z'^2) | c3 = -z''/(60 z'^3) | z' (nz each)]
+  int stretched;
+  double dz_lo[3];       // z(-j+1) - z(-j), j = 1..3
+  double dz_hi[3];       // z(nz-1+j) - z(nz-2+j), j = 1..3
+  double pf_dist[2][3];  // below: -f_bot (z(0) - z(-j)); above: z(nz-1+j) - z(nz-1)
+  double dxy_min;
+  const double* ztab;
 };
+
+// offsets in KParams::ztab
+__host__ __device__ inline int zt_c1(const KParams& p) { return p.nz + 6; }
+__host__ __device__ inline int zt_c2(const KParams& p) { return 2 * p.nz + 6; }
+__host__ __device__ inline int zt_c3(const KParams& p) { return 3 * p.nz + 6; }
+__host__ __device__ inline int zt_zp(const KParams& p) { return 4 * p.nz + 6; }
+__host__ __device__ inline int zt_size(const KParams& p) { return 5 * p.nz + 6; }
+
+// height of plane k (k = -3 .. nz+2; k uniform across the wave).  The table
+// is read through the constant address space: a scalar load, which the
+// kernels' in-flight global->LDS copies do not hold up (a vector load here
+// would make the plane loop wait for them)
+__device__ __forceinline__ double zk(const KParams& p, int k) {
+  if (!p.stretched) return p.z0 + k * p.dz;
+  const __attribute__((address_space(4))) double* t =
+      (const __attribute__((address_space(4))) double*)p.ztab;
+  return t[k + 3];
+}
 
 // Per-substage arguments of the Runge-Kutta update.
 struct StageArgs {
@@ -84,6 +112,9 @@ hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, doub
                              const double* uh, StageArgs st, int read_dF, int write_dF,
                              hipStream_t s);
 hipError_t launch_fill_periodic_z(const KParams& p, double* f, hipStream_t s);
+// B_z on the plane (1 - a) z_k0 + a z_k0+1 (any grid)
+hipError_t launch_bz_plane_k(const KParams& p, const double* f, int k0, double a, double* dst,
+                             hipStream_t s);
 hipError_t launch_fill_solar_columns(const KParams& p, double* f, hipStream_t s);
 hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch,
                                    hipStream_t s);

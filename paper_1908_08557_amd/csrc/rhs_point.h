@@ -77,7 +77,7 @@ __device__ inline S sine_cutoff(S x, double start, double width) {
 
 // height cutoff c_z of the Newtonian cooling at plane k (z_k = z0 + k dz)
 __device__ inline double nc_height_cut(const KParams& p, int k) {
-  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(p.z0 + k * p.dz, p.nc_z0, p.nc_zw);
+  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(zk(p, k), p.nc_z0, p.nc_zw);
 }
 
 // the initial profiles of the Newtonian cooling through the kernel parameters

@@ -264,7 +264,7 @@ __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double
   w = 0.0;
   dw = 0.0;
   if (!p.solar || (p.eta_s == 0.0 && p.chi_s == 0.0 && p.chi_rho == 0.0)) return;
-  const double z = p.z0 + k * p.dz;
+  const double z = zk(p, k);
   const double L = p.z_t - p.z_s;
   double s = (z - p.z_s) / L;
   s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
@@ -274,8 +274,10 @@ __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double
 
 // ---------------------------------------------------------------------------
 // z derivatives: one thread per (column, field), marching over a chunk of
-// planes with the 7-plane window in registers
-template <typename Real>
+// planes with the 7-plane window in registers.  STRETCH: the stencils act in
+// the plane index and the metric of the non-uniform grid scales them,
+// d/dz = c1 S1, d2/dz2 = c2 S2 + c3 S1 (S1, S2 the unscaled stencil sums)
+template <typename Real, bool STRETCH>
 __global__ __launch_bounds__(256) void k_zderiv(const double* __restrict__ f,
                                                 Real* __restrict__ dz, const KParams p,
                                                 int kfirst, int klast, int kchunk) {
@@ -292,9 +294,16 @@ __global__ __launch_bounds__(256) void k_zderiv(const double* __restrict__ f,
   double w3 = a[(k0 + 3) * sp], w4 = a[(k0 + 4) * sp], w5 = a[(k0 + 5) * sp];
   for (int k = k0; k < k1; ++k) {
     const double w6 = a[(k + 6) * sp];
-    const double d1 = (45.0 * (w4 - w2) - 9.0 * (w5 - w1) + (w6 - w0)) * p.i60dz;
-    const double d2 = (-490.0 * w3 + 270.0 * (w4 + w2) - 27.0 * (w5 + w1) + 2.0 * (w6 + w0)) *
-                      p.i180dz2;
+    double d1, d2;
+    if (STRETCH) {
+      const double s1 = 45.0 * (w4 - w2) - 9.0 * (w5 - w1) + (w6 - w0);
+      const double s2 = -490.0 * w3 + 270.0 * (w4 + w2) - 27.0 * (w5 + w1) + 2.0 * (w6 + w0);
+      d1 = s1 * p.ztab[zt_c1(p) + k];
+      d2 = s2 * p.ztab[zt_c2(p) + k] + s1 * p.ztab[zt_c3(p) + k];
+    } else {
+      d1 = (45.0 * (w4 - w2) - 9.0 * (w5 - w1) + (w6 - w0)) * p.i60dz;
+      d2 = (-490.0 * w3 + 270.0 * (w4 + w2) - 27.0 * (w5 + w1) + 2.0 * (w6 + w0)) * p.i180dz2;
+    }
     o1[k * sp] = Real(d1);
     o2[k * sp] = Real(d2);
     w0 = w1;
@@ -530,8 +539,12 @@ hipError_t launch_zderiv_typed(const KParams& p, const double* f, void* dz, int 
   const int kchunk = 32;
   const int nchunk = (k1 - k0 + kchunk - 1) / kchunk;
   dim3 grid(unsigned(p.splane / 256), NF, nchunk);
-  hipLaunchKernelGGL(k_zderiv<Real>, grid, dim3(256), 0, s, f, static_cast<Real*>(dz), p, k0, k1,
-                     kchunk);
+  if (p.stretched)
+    hipLaunchKernelGGL((k_zderiv<Real, true>), grid, dim3(256), 0, s, f, static_cast<Real*>(dz),
+                       p, k0, k1, kchunk);
+  else
+    hipLaunchKernelGGL((k_zderiv<Real, false>), grid, dim3(256), 0, s, f, static_cast<Real*>(dz),
+                       p, k0, k1, kchunk);
   return hipGetLastError();
 }
 
