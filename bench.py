@@ -147,6 +147,45 @@ def driver_bench(w, dt, ms_per_step, reps=5):
             "finite": finite}
 
 
+def split_error(w, nsteps):
+    """Per-field error of the FP32-split form against plain FP64 after nsteps
+    steps from the same state with the same dt (both on the GPU): max |diff|
+    over the interior and the u_x, u_y ghost rows, divided by the max norm of
+    the physical field (A and u as vectors, ln rho, ln T) of the FP64 run."""
+    import torch
+    from paper_1908_08557_amd import cmhd
+    outs = {}
+    dt = None
+    for prec in ("fp64", "fp32_split"):
+        s = cmhd.solver_for(w, prec)
+        st = s.new_state(w.state)
+        if dt is None:
+            dt = s.cfl_dt(st)
+        t = 0.0
+        for _ in range(nsteps):
+            t, _ = s.rk3_step(st, t, dt)
+        torch.cuda.synchronize()
+        outs[prec] = st
+        s.close()
+    a, b = outs["fp64"], outs["fp32_split"]
+    names = ("Ax", "Ay", "Az", "ux", "uy", "uz", "lnrho", "lnT")
+    groups = [(0, 1, 2)] * 3 + [(3, 4, 5)] * 3 + [(6,), (7,)]
+
+    def vals(x, f):
+        v = x[f, 3:-3].reshape(-1)
+        if f in (3, 4):
+            v = torch.cat([x[f, :3].reshape(-1), v])
+        return v
+
+    err = {}
+    for f in range(8):
+        scale = max(float(vals(a, q).abs().max()) for q in groups[f])
+        err[names[f]] = float((vals(b, f) - vals(a, f)).abs().max()) / scale
+    del outs, a, b
+    torch.cuda.empty_cache()
+    return err
+
+
 def cpu_baseline():
     """The oracle as it stands, on a bounded sample: a 128 x 128 x 64 box with
     the 512^2 x 256 box's grid spacing and physics, eight RK3 steps (about
@@ -180,6 +219,8 @@ def main():
     ap.add_argument("--no-driver", action="store_true", help="skip the granulation-driver timing")
     ap.add_argument("--no-stretched", action="store_true",
                     help="skip the same box on the non-uniform z grid")
+    ap.add_argument("--split-error-steps", type=int, default=100,
+                    help="steps of the FP32-split vs FP64 error run (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -248,6 +289,12 @@ def main():
                              "roofline_frac": s["frac"],
                              "substage_ms": s["substage_ms"],
                              "k_zderiv_ms": s["zderiv_ms_per_launch"]}
+        if args.split_error_steps > 0:
+            log(f"[bench] fp32_split vs fp64 error after {args.split_error_steps} steps")
+            e = split_error(w, args.split_error_steps)
+            log(f"[bench] split error: {e}")
+            out["fp32_split"]["rel_err_vs_fp64"] = e
+            out["fp32_split"]["rel_err_steps"] = args.split_error_steps
     tr = measured_traffic() if (w.name == "strat512" and main_prec == "fp64") else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["hbm_bytes_per_substage"]

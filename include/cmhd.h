@@ -153,8 +153,7 @@ cmhd_status cmhd_init_grid(const cmhd_grid* grid, const cmhd_params* params,
  * ghost heights; the upper density follows the recursion of eq. (15) (the
  * mirror form of eq. 13 needs symmetric grid distances).  The time step uses
  * each plane's own spacing min(dx, dy, z'_k).  z = NULL is cmhd_init_grid.
- * The tangent and adjoint steps (cmhd_rk3_step_jvp/vjp, cmhd_bz_plane_vjp)
- * return CMHD_EINVAL on a non-uniform grid. */
+ * The tangent and adjoint steps differentiate the same discrete map. */
 cmhd_status cmhd_init_grid_z(const cmhd_grid* grid, const cmhd_params* params, const double* z,
                              const double* lnrho0_z, const double* lnT0_z, void* stream,
                              cmhd_ctx** out);

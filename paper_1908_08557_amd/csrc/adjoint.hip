@@ -50,16 +50,24 @@ __device__ double st_d1(const KParams& p, const double* g, int f, int x, int y, 
     step3(d, m, a, b, c);
     acc += W1[m - 1] * (gval(p, g, f, x + a, y + b, kz + c) - gval(p, g, f, x - a, y - b, kz - c));
   }
+  // non-uniform z: the plane-index stencil scaled by the metric of plane kz
+  if (d == 2 && p.stretched) return acc * p.ztab[zt_c1(p) + kz - NG];
   return acc * inv60(p, d);
 }
 __device__ double st_d2(const KParams& p, const double* g, int f, int x, int y, int kz, int d) {
   const double W2[3] = {270.0, -27.0, 2.0};
   double acc = -490.0 * gval(p, g, f, x, y, kz);
+  double acc1 = 0.0;
   for (int m = 1; m <= 3; ++m) {
     int a, b, c;
     step3(d, m, a, b, c);
-    acc += W2[m - 1] * (gval(p, g, f, x + a, y + b, kz + c) + gval(p, g, f, x - a, y - b, kz - c));
+    const double hi = gval(p, g, f, x + a, y + b, kz + c), lo = gval(p, g, f, x - a, y - b, kz - c);
+    acc += W2[m - 1] * (hi + lo);
+    acc1 += W1[m - 1] * (hi - lo);
   }
+  // non-uniform z: c2 S2 + c3 S1 at plane kz
+  if (d == 2 && p.stretched)
+    return acc * p.ztab[zt_c2(p) + kz - NG] + acc1 * p.ztab[zt_c3(p) + kz - NG];
   return acc * inv180(p, d);
 }
 __device__ double st_mixed(const KParams& p, const double* g, int f, int x, int y, int kz, int i,
@@ -136,7 +144,7 @@ __device__ void swamp_at(const KParams& p, int k, double& w, double& dw) {
   w = 0.0;
   dw = 0.0;
   if (!p.solar || (p.eta_s == 0.0 && p.chi_s == 0.0 && p.chi_rho == 0.0)) return;
-  const double z = p.z0 + k * p.dz;
+  const double z = zk(p, k);
   const double L = p.z_t - p.z_s;
   double s = (z - p.z_s) / L;
   s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
@@ -251,8 +259,22 @@ __device__ __forceinline__ double qb(const KParams& p, const double* Qb, int slo
   return Qb[slot * (long long)p.nz * p.splane + (long long)k * p.splane +
             (long long)wrapi(y, p.ny) * p.nx + wrapi(x, p.nx)];
 }
+// qbar of zone k scaled by the z metric table entry at offset `off` (zero
+// outside the interior, as qbar)
+__device__ __forceinline__ double qbm(const KParams& p, const double* Qb, int slot, int x, int y,
+                                      int k, int off) {
+  if (k < 0 || k >= p.nz) return 0.0;
+  return p.ztab[off + k] * qb(p, Qb, slot, x, y, k);
+}
 __device__ double qb_d1(const KParams& p, const double* Qb, int slot, int x, int y, int k, int d) {
   double acc = 0.0;
+  if (d == 2 && p.stretched) {
+    // (diag(c1) S1)^T = S1^T diag(c1): the metric belongs to the zone of qbar
+    const int o1 = zt_c1(p);
+    for (int m = 1; m <= 3; ++m)
+      acc += W1[m - 1] * (qbm(p, Qb, slot, x, y, k + m, o1) - qbm(p, Qb, slot, x, y, k - m, o1));
+    return acc;
+  }
   for (int m = 1; m <= 3; ++m) {
     int a, b, c;
     step3(d, m, a, b, c);
@@ -262,6 +284,16 @@ __device__ double qb_d1(const KParams& p, const double* Qb, int slot, int x, int
 }
 __device__ double qb_d2(const KParams& p, const double* Qb, int slot, int x, int y, int k, int d) {
   const double W2[3] = {270.0, -27.0, 2.0};
+  if (d == 2 && p.stretched) {
+    // (diag(c2) S2 + diag(c3) S1)^T = S2 diag(c2) - S1 diag(c3)
+    const int o2 = zt_c2(p), o3 = zt_c3(p);
+    double acc = -490.0 * qbm(p, Qb, slot, x, y, k, o2);
+    for (int m = 1; m <= 3; ++m) {
+      acc += W2[m - 1] * (qbm(p, Qb, slot, x, y, k + m, o2) + qbm(p, Qb, slot, x, y, k - m, o2));
+      acc -= W1[m - 1] * (qbm(p, Qb, slot, x, y, k + m, o3) - qbm(p, Qb, slot, x, y, k - m, o3));
+    }
+    return acc;
+  }
   double acc = -490.0 * qb(p, Qb, slot, x, y, k);
   for (int m = 1; m <= 3; ++m) {
     int a, b, c;
@@ -336,13 +368,25 @@ __global__ __launch_bounds__(256) void k_fill_solar_columns_lin(const KParams p,
     }
     for (int j = 1; j <= NG; ++j) {
       const int up = kb - j + 1;
-      const double fac = 1.0 + p.dz * p.g_z / (p.R * exp(lT0[up * sp]));
+      const double fac = 1.0 + p.dz_lo[j - 1] * p.g_z / (p.R * exp(lT0[up * sp]));
       lT[(kb - j) * sp] = fac * lT[up * sp] + lr[up * sp] - lr[(kb - j) * sp];
     }
-    const double Ttop = exp(lT0[kt * sp]);
-    for (int j = 1; j <= NG; ++j) {
-      lT[(kt + j) * sp] = lT[(kt - j) * sp];
-      lr[(kt + j) * sp] = lr[(kt - j) * sp] - p.g_z * (2.0 * j * p.dz) / (p.R * Ttop) * lT[kt * sp];
+    if (!p.stretched) {
+      const double Ttop = exp(lT0[kt * sp]);
+      for (int j = 1; j <= NG; ++j) {
+        lT[(kt + j) * sp] = lT[(kt - j) * sp];
+        lr[(kt + j) * sp] =
+            lr[(kt - j) * sp] - p.g_z * (2.0 * j * p.dz) / (p.R * Ttop) * lT[kt * sp];
+      }
+    } else {
+      // eq. (15): lr_j = lr_{j-1} + K_j / (T_{j-1} + T_j), K_j = 2 g dz_hi / R
+      for (int j = 1; j <= NG; ++j) lT[(kt + j) * sp] = lT[(kt - j) * sp];
+      for (int j = 1; j <= NG; ++j) {
+        const double Ta = exp(lT0[(kt + j - 1) * sp]), Tb = exp(lT0[(kt + j) * sp]);
+        const double c = -2.0 * p.g_z * p.dz_hi[j - 1] / (p.R * (Ta + Tb) * (Ta + Tb));
+        lr[(kt + j) * sp] =
+            lr[(kt + j - 1) * sp] + c * (Ta * lT[(kt + j - 1) * sp] + Tb * lT[(kt + j) * sp]);
+      }
     }
   }
 }
@@ -377,17 +421,37 @@ __global__ __launch_bounds__(256) void k_fold_solar(const KParams p, const doubl
     const double* lT0 = g + LT * p.sfield + col;
     for (int j = NG; j >= 1; --j) {
       const int up = kb - j + 1;
-      const double fac = 1.0 + p.dz * p.g_z / (p.R * exp(lT0[up * sp]));
+      const double fac = 1.0 + p.dz_lo[j - 1] * p.g_z / (p.R * exp(lT0[up * sp]));
       gT[j - 1] += fac * gT[j];
       if (j == 1) X(LR, kb) += gT[j];   // d ln T(-1) / d ln rho(0)
     }
     X(LT, kb) += gT[0] - G(LT, kb);   // the interior value was already added
-    // ln T above symmetric; ln rho above hydrostatic mirror (depends on T(nz-1))
-    const double Ttop = exp(lT0[kt * sp]);
-    for (int j = 1; j <= NG; ++j) {
-      X(LT, kt - j) += G(LT, kt + j);
-      X(LR, kt - j) += G(LR, kt + j);
-      X(LT, kt) += -p.g_z * (2.0 * j * p.dz) / (p.R * Ttop) * G(LR, kt + j);
+    if (!p.stretched) {
+      // ln T above symmetric; ln rho above hydrostatic mirror (depends on T(nz-1))
+      const double Ttop = exp(lT0[kt * sp]);
+      for (int j = 1; j <= NG; ++j) {
+        X(LT, kt - j) += G(LT, kt + j);
+        X(LR, kt - j) += G(LR, kt + j);
+        X(LT, kt) += -p.g_z * (2.0 * j * p.dz) / (p.R * Ttop) * G(LR, kt + j);
+      }
+    } else {
+      // reverse the eq. (15) recursion (j = 3, 2, 1): the density cotangent
+      // runs down to ln rho(nz-1) and feeds the ln T of both planes of each
+      // step; the ghost ln T then folds back by the mirror of eq. (11)
+      double gR = 0.0;
+      double gTg[NG + 1];
+      gTg[0] = 0.0;
+      for (int j = 1; j <= NG; ++j) gTg[j] = G(LT, kt + j);
+      for (int j = NG; j >= 1; --j) {
+        gR += G(LR, kt + j);
+        const double Ta = exp(lT0[(kt + j - 1) * sp]), Tb = exp(lT0[(kt + j) * sp]);
+        const double c = -2.0 * p.g_z * p.dz_hi[j - 1] / (p.R * (Ta + Tb) * (Ta + Tb));
+        gTg[j - 1] += c * Ta * gR;
+        gTg[j] += c * Tb * gR;
+      }
+      X(LR, kt) += gR;
+      X(LT, kt) += gTg[0];
+      for (int j = 1; j <= NG; ++j) X(LT, kt - j) += gTg[j];
     }
   }
 }
@@ -438,10 +502,10 @@ __global__ __launch_bounds__(256) void k_pf_filter_T(const KParams p, const doub
     const long long col = i - q * sp;
     const int iy = int(col / p.nx), ix = int(col - (long long)iy * p.nx);
     const double k = kabs(p, ix, iy);
-    const double per = q < 2 ? -p.f_bot * p.dz : p.dz;
+    const double* dist = p.pf_dist[q < 2 ? 0 : 1];
     double2 acc = make_double2(0.0, 0.0);
     for (int j = 1; j <= NG; ++j) {
-      const double fac = exp(-k * (j * per)) * inv_n;
+      const double fac = exp(-k * dist[j - 1]) * inv_n;
       const double2 v = S[(q * NG + j - 1) * sp + col];
       acc.x += v.x * fac;
       acc.y += v.y * fac;
@@ -652,6 +716,12 @@ hipError_t launch_copy_state_entries(const KParams& p, const double* src, double
                                      hipStream_t s) {
   hipLaunchKernelGGL(k_copy_state_entries, dim3(grid_of((long long)NF * p.sfield, 256)), dim3(256),
                      0, s, p, src, dst);
+  return hipGetLastError();
+}
+hipError_t launch_bz_plane_vjp_k(const KParams& p, int k0, double a, const double* bzbar,
+                                 double* Xbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_bz_plane_vjp, dim3(grid_of(p.splane, 256)), dim3(256), 0, s, p, k0, a, bzbar,
+                     Xbar);
   return hipGetLastError();
 }
 hipError_t launch_bz_plane_vjp(const KParams& p, double zq, const double* bzbar, double* Xbar,

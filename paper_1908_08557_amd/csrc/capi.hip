@@ -518,6 +518,19 @@ hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which)
   return e;
 }
 
+// the interior planes k0, k0+1 around height z and the weight a of k0+1
+// (non-uniform grids); false outside the interior
+bool plane_between(const cmhd_ctx* c, double z, int* k0, double* a) {
+  const int nz = c->kp.nz;
+  const double* zi = c->z_host.data() + NG;
+  if (!(z >= zi[0]) || !(z <= zi[nz - 1])) return false;
+  int k = int(std::upper_bound(zi, zi + nz, z) - zi) - 1;
+  k = std::min(k, nz - 2);
+  *k0 = k;
+  *a = (z - zi[k]) / (zi[k + 1] - zi[k]);
+  return true;
+}
+
 // the nudging target of a substage at time ts (snapshot pair: interpolated
 // into the u* buffer; single target: nothing to do)
 hipError_t driver_at(cmhd_ctx* c, double ts) {
@@ -644,11 +657,9 @@ cmhd_status cmhd_bz_plane(cmhd_ctx* c, const double* state, double z, double* ds
       return fail(c, CMHD_EINVAL, "z outside the interior");
     return hip_check(c, launch_bz_plane(p, state, z, dst, c->stream), "bz_plane launch");
   }
-  const double* zi = c->z_host.data() + NG;
-  if (!(z >= zi[0]) || !(z <= zi[p.nz - 1])) return fail(c, CMHD_EINVAL, "z outside the interior");
-  int k0 = int(std::upper_bound(zi, zi + p.nz, z) - zi) - 1;
-  k0 = std::min(k0, p.nz - 2);
-  const double a = (z - zi[k0]) / (zi[k0 + 1] - zi[k0]);
+  int k0;
+  double a;
+  if (!plane_between(c, z, &k0, &a)) return fail(c, CMHD_EINVAL, "z outside the interior");
   return hip_check(c, launch_bz_plane_k(p, state, k0, a, dst, c->stream), "bz_plane launch");
 }
 
@@ -685,8 +696,6 @@ size_t adj_layout(const cmhd_ctx* c, size_t off[8]) {
 cmhd_status need_adj(cmhd_ctx* c) {
   cmhd_status st = need_ws(c);
   if (st != CMHD_OK) return st;
-  if (c->kp.stretched)
-    return fail(c, CMHD_EINVAL, "the tangent and adjoint steps support uniform z grids only");
   if (!c->aws) return fail(c, CMHD_ESTATE, "no adjoint workspace bound");
   return CMHD_OK;
 }
@@ -809,11 +818,16 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* c, double* x, double t, double dt, const
 cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* c, double z, const double* bzbar, double* xbar) {
   if (!c || !bzbar || !xbar) return CMHD_EINVAL;
   const KParams& p = c->kp;
-  if (p.stretched)
-    return fail(c, CMHD_EINVAL, "the adjoint supports uniform z grids only");
-  if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
-    return fail(c, CMHD_EINVAL, "z outside the interior");
-  return hip_check(c, launch_bz_plane_vjp(p, z, bzbar, xbar, c->stream), "bz_plane_vjp launch");
+  if (!p.stretched) {
+    if (!(z >= p.z0) || !(z <= p.z0 + (p.nz - 1) * p.dz))
+      return fail(c, CMHD_EINVAL, "z outside the interior");
+    return hip_check(c, launch_bz_plane_vjp(p, z, bzbar, xbar, c->stream), "bz_plane_vjp launch");
+  }
+  int k0;
+  double a;
+  if (!plane_between(c, z, &k0, &a)) return fail(c, CMHD_EINVAL, "z outside the interior");
+  return hip_check(c, launch_bz_plane_vjp_k(p, k0, a, bzbar, xbar, c->stream),
+                   "bz_plane_vjp launch");
 }
 
 cmhd_status cmhd_profile_enable(cmhd_ctx* c, int enable) {

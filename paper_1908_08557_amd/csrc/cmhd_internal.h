@@ -154,6 +154,8 @@ hipError_t launch_copy_state_entries(const KParams& p, const double* src, double
                                      hipStream_t s);
 hipError_t launch_bz_plane_vjp(const KParams& p, double zq, const double* bzbar, double* Xbar,
                                hipStream_t s);
+hipError_t launch_bz_plane_vjp_k(const KParams& p, int k0, double a, const double* bzbar,
+                                 double* Xbar, hipStream_t s);
 
 // uh = u0 + w (u1 - u0) over the two driver planes [2][ny][nx]
 hipError_t launch_driver_interp(const KParams& p, const double* u0, const double* u1, double w,

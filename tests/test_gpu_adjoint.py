@@ -47,6 +47,7 @@ CASES = {
     "strat32x16x10_norad": lambda: _norad(W.small_stratified(32, 16, 10, Lxy=10.0, z1=8.0)),
     "periodic16": lambda: W.periodic_box(16, nmodes=6, amp_u=1e-2),
     "strat32x32x24_newton": lambda: _newton(),
+    "stretch32x32x12": lambda: W.small_stretched(32, 32, 12, t_ramp=0.06),
 }
 
 
@@ -85,7 +86,8 @@ def test_dot_product_tlm_vs_adjoint(case):
     assert float(dy[~mask].abs().max()) == 0.0 and float(xbar[~mask].abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("case", ["strat32x32x12", "periodic16", "strat32x32x24_newton"])
+@pytest.mark.parametrize("case", ["strat32x32x12", "periodic16", "strat32x32x24_newton",
+                                  "stretch32x32x12"])
 def test_tlm_matches_oracle_complex_step(case):
     import torch
     w = CASES[case]()
@@ -108,13 +110,18 @@ def test_tlm_matches_oracle_complex_step(case):
     assert_parity(got, ref, solar, 1e-10, f"TLM {case}")
 
 
-def test_loss_gradient_matches_oracle():
+@pytest.mark.parametrize("grid", ["uniform", "stretched"])
+def test_loss_gradient_matches_oracle(grid):
     # dL/du* . v from the adjoint rollout against the oracle's complex step
+    # (on the stretched grid the B_z plane lies between non-uniform planes)
     import torch
 
     from paper_1908_08557_amd import adjoint as A
-    w = _norad(W.small_stratified(32, 32, 16, Lxy=12.0, z1=12.0, nbip=2, t_ramp=0.0))
-    print("[case] loss gradient vs oracle", flush=True)
+    if grid == "uniform":
+        w = _norad(W.small_stratified(32, 32, 16, Lxy=12.0, z1=12.0, nbip=2, t_ramp=0.0))
+    else:
+        w = _norad(W.small_stretched(32, 32, 16, Lxy=12.0, nbip=2, t_ramp=0.0))
+    print(f"[case] loss gradient vs oracle ({grid} z)", flush=True)
     dt = oracle_dt(w)
     zq, nsteps = 2.0, 4
     F = O.from_compact(w.state)

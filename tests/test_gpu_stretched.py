@@ -2,7 +2,8 @@
 corona to the chromosphere): the library's step against the oracle on the
 same seeded stretched boxes (float64: 1e-12 per field after one step, 1e-11
 after ten; FP32-split at its own tolerance), the time step, the B_z plane,
-the pipelined substage, and the refusal of the adjoint."""
+and the pipelined substage (the tangent and adjoint on stretched grids are
+in the adjoint tests)."""
 import numpy as np
 import pytest
 
@@ -100,16 +101,3 @@ def test_stretched_pipelined_substage():
     dt = oracle_dt(w)
     assert_parity(_gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
                   "stretched pipelined 1 step")
-
-
-def test_stretched_adjoint_is_refused():
-    import torch
-    from paper_1908_08557_amd import cmhd
-    w = W.small_stretched(32, 32, 12)
-    s = cmhd.solver_for(w)
-    s.bind_adjoint()
-    x = s.new_state(w.state)
-    with pytest.raises(cmhd.CmhdError) as e:
-        s.rk3_step_vjp(x, 0.0, 1e-9, torch.zeros_like(x))
-    assert e.value.code == cmhd.CMHD_EINVAL
-    s.close()
