@@ -10,7 +10,7 @@
 // The pointwise P is the same templated program as the forward kernel
 // (rhs_eval), evaluated on dual numbers; the stencil and ghost transposes are
 // written out here.  Correctness, not speed, is the target of these kernels.
-#include "cmhd_internal.h"
+#include "launch.h"
 #include "dual.h"
 #include "qslots.h"
 #include "rhs_point.h"

@@ -21,7 +21,7 @@
 // spectral filter.  Because the multipliers are real and even in k, two real
 // planes are filtered at once as the real and imaginary parts of one complex
 // plane.
-#include "cmhd_internal.h"
+#include "launch.h"
 
 namespace cmhd {
 namespace {

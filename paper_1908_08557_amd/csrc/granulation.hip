@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "cmhd_internal.h"
+#include "launch.h"
 
 using namespace cmhd;
 

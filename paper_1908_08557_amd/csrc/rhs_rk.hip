@@ -30,7 +30,7 @@
 // The arithmetic of every derivative is that of the product stencils applied
 // to the float64 state (differences formed in float64, then rounded to the
 // precision of the right-hand side).
-#include "cmhd_internal.h"
+#include "launch.h"
 #include "qslots.h"
 #include "rhs_point.h"
 
