@@ -58,3 +58,33 @@ def assert_parity(got, ref, solar, tol, label=""):
     print(f"[parity] {label} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
     assert not bad, f"{label}: fields above {tol}: {bad}"
     return errs
+
+
+def oracle_patch_centre(w, k, j, i, dt, h):
+    """The oracle's value of zone (k, j, i) after one step, from a
+    (2h+1)^3 patch of the initial state around it with periodic wrap at the
+    patch edges.  One RK3 step reaches 9 zones (three substages of 3-zone
+    stencils), so for h >= 9 + 3 and a zone at least h planes away from the
+    z boundaries and below the swamp layer the wrap does not reach the
+    centre and the value equals that of the whole-box step."""
+    g, p = w.grid, w.params
+    n = 2 * h + 1
+    ys = np.arange(j - h, j + h + 1) % g["ny"]
+    xs = np.arange(i - h, i + h + 1) % g["nx"]
+    kz = np.arange(k - h, k + h + 1) + NG
+    patch = w.state[:, kz][:, :, ys][:, :, :, xs]
+    dx, dy = g["Lx"] / g["nx"], g["Ly"] / g["ny"]
+    zall = O.zk(g)
+    grid = dict(nx=n, ny=n, nz=n, Lx=n * dx, Ly=n * dy, zbc="periodic")
+    if "z" in g:
+        # heights of the patch planes and of the planes its stencils reach
+        grid.update(z=zall[k - h:k + h + 1 + 2 * NG], z0=zall[k - h + NG], z1=zall[k + h + NG])
+    else:
+        dz = O.spacings(g)[2]
+        grid.update(z0=zall[k - h + NG], z1=zall[k - h + NG] + n * dz)
+    state = np.zeros((8, n + 2 * NG, n, n))
+    state[:, NG:NG + n] = patch
+    F = O.from_compact(state)
+    O.fill_ghosts(F, grid, p, None)
+    F = O.rk3_step(F, 0.0, dt, grid, p, None, None)
+    return F[:, NG + h, NG + h, NG + h]

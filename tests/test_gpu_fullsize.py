@@ -1,0 +1,79 @@
+"""GPU parity at the benchmark's full size, in the launch configuration that
+bench.py times (512 x 512 x 256, pipelined substage, XCD-ordered tiles), on
+sampled outputs: one step of the whole box on the GPU, and for each sampled
+zone the oracle run on a 25^3 patch around it.  After one RK3 step a zone
+depends on the state within 9 zones (three substages of the 3-zone stencils),
+so a patch that reaches 12 zones out, with periodic wrap at its edges, gives
+the oracle's value of its centre exactly (up to rounding); samples stay 12
+zones away from the photosphere and below the swamp layer, where the solar
+boundary rules would enter."""
+import numpy as np
+import pytest
+
+from oracle import mhd as O
+from paper_1908_08557_amd import workloads as W
+from parity_util import GROUPS, NAMES, NG, oracle_patch_centre
+
+pytestmark = pytest.mark.gpu
+
+H = 12          # patch half-width
+NSAMPLE = 16
+
+
+def _gpu_one_step(w, precision):
+    import torch
+    from paper_1908_08557_amd import cmhd
+    s = cmhd.solver_for(w, precision)
+    st = s.new_state(w.state)
+    dt = s.cfl_dt(st)
+    t, _ = s.rk3_step(st, 0.0, dt)
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    s.close()
+    del st
+    torch.cuda.empty_cache()
+    return out, dt
+
+
+def _samples(w, seed):
+    g, p = w.grid, w.params
+    z = O.zk(g)[NG:NG + g["nz"]]
+    kmax = int(np.searchsorted(z, p["z_s"])) - 1 - H
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(H, kmax + 1, NSAMPLE)
+    ks[0], ks[1] = H, kmax                      # both ends of the allowed range
+    js = rng.integers(0, g["ny"], NSAMPLE)
+    is_ = rng.integers(0, g["nx"], NSAMPLE)
+    is_[2], js[2] = g["nx"] - 1, 0              # a patch that wraps in x and y
+    return list(zip(ks, js, is_))
+
+
+def _check(w, got, dt, tol, label):
+    scales = []
+    for f in range(8):
+        scales.append(max(np.max(np.abs(got[q, NG:-NG])) for q in GROUPS[f]))
+    worst = np.zeros(8)
+    for (k, j, i) in _samples(w, 11):
+        ref = oracle_patch_centre(w, int(k), int(j), int(i), dt, H)
+        val = got[:, NG + k, j, i]
+        worst = np.maximum(worst, np.abs(val - ref) / np.array(scales))
+    print(f"[parity] {label} sampled: " + " ".join(f"{NAMES[f]}={worst[f]:.2e}" for f in range(8)),
+          flush=True)
+    assert np.all(worst <= tol), (label, dict(zip(NAMES, worst)))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_split", 2e-6)])
+def test_strat512_one_step_sampled(precision, tol):
+    w = W.strat512()
+    print(f"[case] strat512 one step {precision}, {NSAMPLE} sampled zones", flush=True)
+    got, dt = _gpu_one_step(w, precision)
+    _check(w, got, dt, tol, f"strat512 {precision}")
+
+
+@pytest.mark.timeout(900)
+def test_strat512_stretched_one_step_sampled():
+    w = W.strat512_stretched()
+    print(f"[case] strat512_stretched one step fp64, {NSAMPLE} sampled zones", flush=True)
+    got, dt = _gpu_one_step(w, "fp64")
+    _check(w, got, dt, 1e-12, "strat512_stretched fp64")

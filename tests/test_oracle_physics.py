@@ -612,3 +612,24 @@ def test_cfl_dt_limits():
     assert abs(O.cfl_dt(F, w.grid, w.params) - 0.4 * h / (0.5 + cs)) < 1e-15
     w.params.update(nu=10.0)
     assert abs(O.cfl_dt(F, w.grid, w.params) - 0.12 * h * h / 10.0) < 1e-15
+
+
+@pytest.mark.parametrize("stretch", [False, True])
+def test_patch_step_equals_whole_box_step(stretch):
+    # the sampled full-size parity test rests on locality: one step of a
+    # 25^3 periodic patch gives the whole-box step at its centre
+    from parity_util import oracle_patch_centre
+    if stretch:
+        w = W.small_stretched(32, 32, 40, Lxy=20.0, nbip=2)
+    else:
+        w = W.small_stratified(32, 32, 40, Lxy=20.0, z1=30.0, nbip=2)
+    F = O.from_compact(w.state)
+    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
+    dt = O.cfl_dt(F, w.grid, w.params)
+    full = O.to_compact(O.rk3_step(F, 0.0, dt, w.grid, w.params, w.lnrho0_z,
+                                   dict(uh=w.uh_target, ah=w.ah_target)))
+    fmax = np.max(np.abs(full[:, NG:-NG]), axis=(1, 2, 3))
+    for (k, j, i) in [(12, 5, 7), (20, 31, 0), (14, 16, 30)]:
+        got = oracle_patch_centre(w, k, j, i, dt, 12)
+        ref = full[:, NG + k, j, i]
+        assert np.all(np.abs(got - ref) <= 1e-13 * np.maximum(fmax, 1e-30)), (k, j, i, got - ref)
