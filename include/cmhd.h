@@ -51,6 +51,8 @@ typedef enum {
   CMHD_EINVAL = -1,      /* invalid argument (sizes, parameters, pointers) */
   CMHD_EDEVICE = -2,     /* a HIP runtime call failed */
   CMHD_ENONFINITE = -3,  /* a non-finite value was found (cmhd_check_finite) */
+  CMHD_EDT = -4,         /* the time step from the CFL limits is zero or not finite
+                            although the state is finite (cmhd_cfl_dt) */
   CMHD_ESTATE = -5,      /* call out of order (e.g. no workspace bound) */
   CMHD_EWORKSPACE = -6   /* workspace too small */
 } cmhd_status;
@@ -226,6 +228,16 @@ cmhd_status cmhd_cfl_dt(cmhd_ctx* ctx, double* state, double* dt_out);
  * dst_on_host != 0: dst is host memory and the call is synchronous. */
 cmhd_status cmhd_get_fields(cmhd_ctx* ctx, const double* state, unsigned mask,
                             double* dst, int dst_on_host, int with_ghosts);
+
+/* The inverse of cmhd_get_fields: copy the fields selected by mask (bit f =
+ * field f) from src into the device state, src packed in field order as
+ * [nsel][nz][ny][nx] (with_ghosts = 0: the interior planes; the ghost planes
+ * keep their values) or [nsel][nz+6][ny][nx] (with_ghosts != 0: every plane,
+ * which restores the u_x, u_y ghost rows that are state in solar mode).
+ * src_on_host != 0: src is host memory and the call is synchronous; else the
+ * copies are queued on the context stream. */
+cmhd_status cmhd_set_fields(cmhd_ctx* ctx, double* state, unsigned mask, const double* src,
+                            int src_on_host, int with_ghosts);
 
 /* B_z = d_x A_y - d_y A_x + Bext_z on the horizontal plane at height z,
  * linear between the two enclosing grid planes, into device dst [ny][nx]. */

@@ -16,7 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libcmhd.so")
 
-CMHD_OK, CMHD_EINVAL, CMHD_EDEVICE, CMHD_ENONFINITE = 0, -1, -2, -3
+CMHD_OK, CMHD_EINVAL, CMHD_EDEVICE, CMHD_ENONFINITE, CMHD_EDT = 0, -1, -2, -3, -4
 CMHD_ESTATE, CMHD_EWORKSPACE = -5, -6
 CMHD_FP64, CMHD_FP32_SPLIT = 0, 1
 CMHD_ZBC_PERIODIC, CMHD_ZBC_SOLAR = 0, 1
@@ -86,6 +86,7 @@ def load():
         "cmhd_cfl_dt": (I, [P, P, ctypes.POINTER(D)]),
         "cmhd_eval_rhs": (I, [P, P, D, P]),
         "cmhd_get_fields": (I, [P, P, U, P, I, I]),
+        "cmhd_set_fields": (I, [P, P, U, P, I, I]),
         "cmhd_bz_plane": (I, [P, P, D, P]),
         "cmhd_check_finite": (I, [P, P]),
         "cmhd_adjoint_workspace_bytes": (S, [P]),
@@ -120,7 +121,7 @@ def exported_symbols():
     return ["cmhd_init_grid", "cmhd_init_grid_z", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
             "cmhd_set_stream", "cmhd_set_driver", "cmhd_set_driver_snapshots",
             "cmhd_fill_ghosts", "cmhd_rk3_step",
-            "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_bz_plane", "cmhd_check_finite",
+            "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_set_fields", "cmhd_bz_plane", "cmhd_check_finite",
             "cmhd_adjoint_workspace_bytes", "cmhd_bind_adjoint_workspace", "cmhd_rk3_step_jvp",
             "cmhd_rk3_step_vjp", "cmhd_bz_plane_vjp",
             "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy",
@@ -283,6 +284,21 @@ class Solver:
                                              ctypes.c_void_p(out.ctypes.data), 1,
                                              1 if with_ghosts else 0))
         return out
+
+    def set_fields(self, state, src, mask=0xFF, with_ghosts=False):
+        """Copy host fields [nsel, nz(+6), ny, nx] (the layout of get_fields)
+        into the device state."""
+        self._stream()
+        nsel = bin(mask & 0xFF).count("1")
+        g = self.grid
+        nzc = g["nz"] + 6 if with_ghosts else g["nz"]
+        a = np.ascontiguousarray(src, dtype=np.float64)
+        if a.shape != (nsel, nzc, g["ny"], g["nx"]):
+            raise ValueError(f"src must have shape {(nsel, nzc, g['ny'], g['nx'])}")
+        self._check(self.lib.cmhd_set_fields(self.ctx, self._state(state), mask,
+                                             ctypes.c_void_p(a.ctypes.data), 1,
+                                             1 if with_ghosts else 0))
+        return state
 
     def bz_plane(self, state, z, out=None):
         self._stream()

@@ -263,9 +263,10 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
   double tau = p.solar ? std::fmax(p.tau_u, p.tau_A) : 0.0;
   tau = std::fmax(tau, p.nc_tau);
   if (tau > 0.0) dt = std::fmin(dt, p.c_nudge / tau);
-  if (!(dt > 0.0) || !std::isfinite(dt) || std::isnan(m[0]) || std::isnan(m[1]) ||
-      std::isnan(m[2]))
-    return fail(c, CMHD_ENONFINITE, "time step is not finite (state holds NaN/Inf?)");
+  if (std::isnan(m[0]) || std::isnan(m[1]) || std::isnan(m[2]))
+    return fail(c, CMHD_ENONFINITE, "the state holds a non-finite value (CFL maxima are NaN)");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(c, CMHD_EDT, "the time step from the CFL limits is " + std::to_string(dt));
   *dt_out = dt;
   return CMHD_OK;
 }
@@ -646,6 +647,28 @@ cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, dou
     o += per;
   }
   if (dst_on_host) return hip_check(c, hipStreamSynchronize(c->stream), "get_fields sync");
+  return CMHD_OK;
+}
+
+cmhd_status cmhd_set_fields(cmhd_ctx* c, double* state, unsigned mask, const double* src,
+                            int src_on_host, int with_ghosts) {
+  if (!c || !state || !src) return CMHD_EINVAL;
+  if (mask == 0 || mask > 0xFFu) return fail(c, CMHD_EINVAL, "mask selects no valid field");
+  const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
+  const size_t nzc = with_ghosts ? size_t(c->grid.nz + 2 * NG) : size_t(c->grid.nz);
+  const size_t off = with_ghosts ? 0 : NG * plane;
+  const size_t per = nzc * plane;
+  const size_t sfield = size_t(c->grid.nz + 2 * NG) * plane;
+  const hipMemcpyKind kind = src_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  size_t o = 0;
+  for (int f = 0; f < NF; ++f) {
+    if (!(mask & (1u << f))) continue;
+    hipError_t e = hipMemcpyAsync(state + f * sfield + off, src + o, per * sizeof(double), kind,
+                                  c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "set_fields copy");
+    o += per;
+  }
+  if (src_on_host) return hip_check(c, hipStreamSynchronize(c->stream), "set_fields sync");
   return CMHD_OK;
 }
 

@@ -347,3 +347,17 @@ def test_fp32_split_close_to_fp64():
     a = gpu_run(w, 100, dt, precision="fp64")
     b = gpu_run(w, 100, dt, precision="fp32_split")
     assert_parity(b, a, True, 1e-5, "fp32_split vs fp64 100 steps")
+
+
+def test_collapsed_time_step_reported():
+    # a finite state whose fast-mode speed and conduction overflow: the CFL
+    # limits give dt = 0 (forced from the host; every kernel exits normally)
+    from paper_1908_08557_amd import cmhd
+    w = W.small_stratified(32, 32, 12)
+    w.state[7, NG + 4, 3, 5] = 709.0          # T ~ 8e307
+    s = cmhd.solver_for(w)
+    st = s.new_state(w.state)
+    assert s.check_finite(st) is True
+    with pytest.raises(cmhd.CmhdError) as e:
+        s.cfl_dt(st)
+    assert e.value.code == cmhd.CMHD_EDT
