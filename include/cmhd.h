@@ -347,15 +347,17 @@ cmhd_status cmhd_gran_bind_workspace(cmhd_gran* g, void* dev_ptr, size_t bytes);
  * the centres with vext_host ([2][ny][nx] host memory, or NULL: centres stay
  * put), remove the granules that have ended, refill.  Births consume
  * unif[0..], xi[0..] (host memory, n_pool uniforms and 2 n_pool variations);
- * *births receives their number.  The host work is sequential; the granule
- * table is then copied to the device (synchronous).  EINVAL when the pool runs
- * out (the granules born until then are kept). */
+ * *births receives their number.  Host work only (sequential; no workspace
+ * needed): the next cmhd_gran_velocity copies the granule table to the
+ * device.  EINVAL when the pool runs out (the granules born until then are
+ * kept). */
 cmhd_status cmhd_gran_update(cmhd_gran* g, double t, const double* vext_host, const double* unif,
                              const double* xi, long long n_pool, long long* births);
 
 /* Driver snapshot at time t from the current population into device
  * uh [2][ny][nx]: granular field, eq. (3) enhancement, eq. (4) rescaling
- * (a zero field when there is no granule).  Asynchronous. */
+ * (a zero field when there is no granule).  Needs a bound workspace.
+ * Asynchronous, except for the copy of the granule table after an update. */
 cmhd_status cmhd_gran_velocity(cmhd_gran* g, double t, double* uh);
 
 /* Host copy of the living granules, rows (x, y, t0, T, v_max, t_max) in birth

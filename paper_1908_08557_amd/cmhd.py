@@ -391,7 +391,9 @@ class Granulation:
     FIELDS = ("r_gran", "r_lane", "r_excl", "t_gran", "v0", "vmin_frac", "life_var", "amp_var",
               "f_rot")
 
-    def __init__(self, params: dict, device: str = "cuda"):
+    def __init__(self, params: dict, device: str = "cuda", workspace: bool = True):
+        """workspace=False: the granule bookkeeping only (update, granules),
+        host work that runs without a GPU; velocity() then raises."""
         self.lib = load()
         self.device = torch.device(device)
         q = CmhdGranParams()
@@ -402,11 +404,14 @@ class Granulation:
         self._q = q
         self.shape = (2, q.ny, q.nx)
         obj = ctypes.c_void_p()
-        stream = torch.cuda.current_stream(self.device).cuda_stream
+        stream = torch.cuda.current_stream(self.device).cuda_stream if workspace else None
         rc = self.lib.cmhd_gran_create(ctypes.byref(q), ctypes.c_void_p(stream), ctypes.byref(obj))
         if rc != CMHD_OK:
             raise CmhdError(rc, "cmhd_gran_create: invalid parameters")
         self.obj = obj
+        self.workspace = None
+        if not workspace:
+            return
         nbytes = self.lib.cmhd_gran_workspace_bytes(obj)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()

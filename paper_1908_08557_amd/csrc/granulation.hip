@@ -21,6 +21,7 @@ struct cmhd_gran {
   std::vector<double> tab;
   bool has_last = false;
   double t_last = 0.0;
+  bool dirty = false;          // the device copy of the table is out of date
   // free-pixel flags and a Fenwick tree over them (k-th free pixel)
   std::vector<uint8_t> free_px;
   std::vector<int> fen;
@@ -384,7 +385,6 @@ cmhd_status cmhd_gran_update(cmhd_gran* g, double t, const double* vext, const d
 #pragma clang fp contract(off)
   if (!g || !births || !std::isfinite(t) || n_pool < 0) return CMHD_EINVAL;
   if ((!unif || !xi) && n_pool > 0) return gfail(g, CMHD_EINVAL, "random pools are NULL");
-  if (!g->ws) return gfail(g, CMHD_ESTATE, "no workspace bound");
   if (g->has_last && t < g->t_last) return gfail(g, CMHD_EINVAL, "time runs backward");
   *births = 0;
   const cmhd_gran_params& p = g->p;
@@ -449,14 +449,7 @@ cmhd_status cmhd_gran_update(cmhd_gran* g, double t, const double* vext, const d
   *births = c;
   g->has_last = true;
   g->t_last = t;
-  const size_t n = g->tab.size();
-  if (n) {
-    hipError_t e = hipMemcpyAsync(g->dtab, g->tab.data(), n * sizeof(double),
-                                  hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess)
-      return gfail(g, CMHD_EDEVICE, std::string("granule table copy: ") + hipGetErrorString(e));
-  }
+  g->dirty = true;
   return st;
 }
 
@@ -466,6 +459,16 @@ cmhd_status cmhd_gran_velocity(cmhd_gran* g, double t, double* uh) {
   const GranDev d = dev_params(g);
   const int n = int(g->tab.size() / kRow);
   hipStream_t s = g->stream;
+  if (g->dirty && n > 0) {
+    // the table as of the last update (synchronous: the host vector may
+    // change at the next update)
+    hipError_t e = hipMemcpyAsync(g->dtab, g->tab.data(), g->tab.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+      return gfail(g, CMHD_EDEVICE, std::string("granule table copy: ") + hipGetErrorString(e));
+  }
+  g->dirty = false;
   // the render writes the granular field into the output, the combination
   // reads it back pixel by pixel before overwriting
   dim3 grid((d.nx + kTile - 1) / kTile, (d.ny + kTile - 1) / kTile);
