@@ -53,3 +53,51 @@ def test_params_marshalling_roundtrip():
     assert p.tau_u == w.params["tau_u"] and p.g_z == -274.0
     g = cmhd.make_grid(w.grid, "fp32_split")
     assert (g.nx, g.ny, g.nz, g.zbc, g.prec) == (64, 64, 64, 1, 1)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_init_rejects_invalid_grids_before_touching_a_device():
+    # parameter validation is host logic: every case returns CMHD_EINVAL on
+    # the CPU (a valid one would go on to look for a gfx950 device)
+    import numpy as np
+
+    from paper_1908_08557_amd import cmhd
+    from paper_1908_08557_amd import workloads as W
+    lib = cmhd.load()
+    w = W.small_stratified(32, 32, 12)
+    n = 12 + 6
+    lr = np.ascontiguousarray(w.lnrho0_z)
+    lt = np.ascontiguousarray(w.lnT0_z)
+    dp = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def init(grid, params, z=None, lnr=lr, lnt=lt):
+        g = cmhd.make_grid(grid)
+        p = cmhd.make_params(params)
+        out = ctypes.c_void_p()
+        zz = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
+        return lib.cmhd_init_grid_z(ctypes.byref(g), ctypes.byref(p), dp(zz), dp(lnr), dp(lnt),
+                                    None, ctypes.byref(out))
+
+    bad_grids = [dict(nx=24), dict(ny=2048), dict(nz=4), dict(Lx=-1.0), dict(z1=-5.0)]
+    for b in bad_grids:
+        g = dict(w.grid)
+        g.update(b)
+        assert init(g, w.params) == cmhd.CMHD_EINVAL, b
+    bad_params = [dict(gamma=1.0), dict(eta=-1.0), dict(z_t=0.0, z_s=1.0),
+                  dict(nc_tau=1.0, nc_lnrho0_z=None)]
+    for b in bad_params:
+        p = dict(w.params)
+        p.update(b)
+        if b.get("nc_tau"):
+            assert init(w.grid, p, lnt=None) == cmhd.CMHD_EINVAL, b
+        else:
+            assert init(w.grid, p) == cmhd.CMHD_EINVAL, b
+    # non-uniform heights: not increasing, or with periodic boundaries
+    z = np.linspace(0.0, 10.0, n)
+    z[7] = z[6]
+    assert init(w.grid, w.params, z=z) == cmhd.CMHD_EINVAL
+    gp = dict(w.grid)
+    gp["zbc"] = "periodic"
+    assert init(gp, w.params, z=np.linspace(0.0, 10.0, n)) == cmhd.CMHD_EINVAL
+    # solar mode without the ln rho0 profile
+    assert init(w.grid, w.params, lnr=None) == cmhd.CMHD_EINVAL
