@@ -1,6 +1,6 @@
 """GPU parity at the benchmark's full size, in the launch configuration that
-bench.py times (512 x 512 x 256, pipelined substage, XCD-ordered tiles), on
-sampled outputs: one step of the whole box on the GPU, and for each sampled
+bench.py times (512 x 512 x 256, pipelined substage, XCD-ordered tiles), and
+on the largest box (1024 x 1024 x 256), on sampled outputs: one step of the whole box on the GPU, and for each sampled
 zone the oracle run on a 25^3 patch around it.  After one RK3 step a zone
 depends on the state within 9 zones (three substages of the 3-zone stencils),
 so a patch that reaches 12 zones out, with periodic wrap at its edges, gives
@@ -77,3 +77,13 @@ def test_strat512_stretched_one_step_sampled():
     print(f"[case] strat512_stretched one step fp64, {NSAMPLE} sampled zones", flush=True)
     got, dt = _gpu_one_step(w, "fp64")
     _check(w, got, dt, 1e-12, "strat512_stretched fp64")
+
+
+@pytest.mark.timeout(1200)
+def test_ar1024_one_step_sampled():
+    # the largest box: 1024^2 x 256 over 64 Mm with 32 bipoles (the 2-D
+    # transforms at their maximum length), FP32-split as in its workload
+    w = W.ar1024()
+    print(f"[case] ar1024 one step fp32_split, {NSAMPLE} sampled zones", flush=True)
+    got, dt = _gpu_one_step(w, "fp32_split")
+    _check(w, got, dt, 2e-6, "ar1024 fp32_split")

@@ -361,3 +361,16 @@ def test_collapsed_time_step_reported():
     with pytest.raises(cmhd.CmhdError) as e:
         s.cfl_dt(st)
     assert e.value.code == cmhd.CMHD_EDT
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("nx,nz", [(128, 37), (256, 37)])
+def test_ragged_z_chunks(nx, nz):
+    # the last z chunk of the fused kernel is short: 128^2 x 37 marches
+    # chunks of 2 planes (19 chunks, the last of 1) in one launch; 256^2 x 37
+    # is pipelined in chunks of 16, 16 and 5 planes
+    w = W.small_stratified(nx, nx, nz, Lxy=nx * 0.3, z1=20.0, nbip=2)
+    dt = oracle_dt(w)
+    print(f"[case] ragged z chunks {nx}x{nx}x{nz}", flush=True)
+    assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
+                  f"ragged {nx}x{nx}x{nz}")
