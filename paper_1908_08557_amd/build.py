@@ -30,6 +30,15 @@ FLAGS = [
 ]
 
 
+# per-source extra flags.  The fused substage kernel is latency-bound at one
+# wave per SIMD; the iterative ILP scheduling strategy orders its plane loop
+# for more overlap (4-5% faster per substage at 512^2 x 256, measured), while
+# it slows the streaming z-derivative pass, which keeps the default.
+SOURCE_FLAGS = {
+    "rhs_rk.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
@@ -40,7 +49,8 @@ def build(verbose: bool = False, extra_flags=()) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, *extra_flags, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), *extra_flags, "-c", src,
+               "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

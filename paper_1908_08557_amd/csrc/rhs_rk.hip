@@ -1,8 +1,5 @@
-// One 2N-RK3 substage in two kernels.
-//
-// k_zderiv streams the state once in z and writes the sixth-order d/dz and
-// d2/dz2 of the 8 fields (16 slots, [slot][nz][ny][nx], in the precision of
-// the right-hand side).
+// The fused kernel of one 2N-RK3 substage (the z derivatives it reads come
+// from k_zderiv, zderiv.hip).
 //
 // k_rhs_rk: one thread per (x, y) column of a 16 x 16 tile, marching in z.
 // Every input it needs at plane k is single-plane data, staged into LDS by
@@ -46,7 +43,6 @@ constexpr int NN = NF - NA;         // u_x u_y u_z ln rho ln T
 constexpr int NZN = 4;              // haloed d/dz of u_x u_y u_z ln T
 constexpr int NON = 6;              // own d/dz ln rho, d2/dz2 of u_x u_y u_z ln rho ln T
 constexpr int NDX = 6;              // xy mixed: A_x A_y A_z u_x u_y ln T
-constexpr int NZSLOT = 2 * NF;      // slots of the z-derivative buffer
 constexpr int PC = NG * RW + NG;    // own point relative to a haloed-plane base
 constexpr int DC = NG * DXW;        // own point relative to the D1_x base
 
@@ -273,49 +269,6 @@ __device__ __forceinline__ void swamp(const KParams& p, int k, double& w, double
 }
 
 // ---------------------------------------------------------------------------
-// z derivatives: one thread per (column, field), marching over a chunk of
-// planes with the 7-plane window in registers.  STRETCH: the stencils act in
-// the plane index and the metric of the non-uniform grid scales them,
-// d/dz = c1 S1, d2/dz2 = c2 S2 + c3 S1 (S1, S2 the unscaled stencil sums)
-template <typename Real, bool STRETCH>
-__global__ __launch_bounds__(256) void k_zderiv(const double* __restrict__ f,
-                                                Real* __restrict__ dz, const KParams p,
-                                                int kfirst, int klast, int kchunk) {
-  const long long sp = p.splane;
-  const long long col = blockIdx.x * 256LL + threadIdx.x;
-  const int fi = blockIdx.y;
-  const int k0 = kfirst + blockIdx.z * kchunk;
-  const int k1 = min(k0 + kchunk, klast);
-  const long long szs = (long long)p.nz * sp;
-  const double* a = f + fi * p.sfield + col;   // array plane j at a[j * sp]
-  Real* o1 = dz + fi * szs + col;
-  Real* o2 = dz + (NF + fi) * szs + col;
-  double w0 = a[(k0 + 0) * sp], w1 = a[(k0 + 1) * sp], w2 = a[(k0 + 2) * sp];
-  double w3 = a[(k0 + 3) * sp], w4 = a[(k0 + 4) * sp], w5 = a[(k0 + 5) * sp];
-  for (int k = k0; k < k1; ++k) {
-    const double w6 = a[(k + 6) * sp];
-    double d1, d2;
-    if (STRETCH) {
-      const double s1 = 45.0 * (w4 - w2) - 9.0 * (w5 - w1) + (w6 - w0);
-      const double s2 = -490.0 * w3 + 270.0 * (w4 + w2) - 27.0 * (w5 + w1) + 2.0 * (w6 + w0);
-      d1 = s1 * p.ztab[zt_c1(p) + k];
-      d2 = s2 * p.ztab[zt_c2(p) + k] + s1 * p.ztab[zt_c3(p) + k];
-    } else {
-      d1 = (45.0 * (w4 - w2) - 9.0 * (w5 - w1) + (w6 - w0)) * p.i60dz;
-      d2 = (-490.0 * w3 + 270.0 * (w4 + w2) - 27.0 * (w5 + w1) + 2.0 * (w6 + w0)) * p.i180dz2;
-    }
-    o1[k * sp] = Real(d1);
-    o2[k * sp] = Real(d2);
-    w0 = w1;
-    w1 = w2;
-    w2 = w3;
-    w3 = w4;
-    w4 = w5;
-    w5 = w6;
-  }
-}
-
-// ---------------------------------------------------------------------------
 template <typename Real, bool SOLAR, bool READ_DF, bool WRITE_DF, bool NEWTON>
 __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                                const Real* __restrict__ dz,
@@ -533,21 +486,6 @@ __global__ void k_ghost_rows(const double* __restrict__ f, double* __restrict__ 
   }
 }
 
-template <typename Real>
-hipError_t launch_zderiv_typed(const KParams& p, const double* f, void* dz, int k0, int k1,
-                               hipStream_t s) {
-  const int kchunk = 32;
-  const int nchunk = (k1 - k0 + kchunk - 1) / kchunk;
-  dim3 grid(unsigned(p.splane / 256), NF, nchunk);
-  if (p.stretched)
-    hipLaunchKernelGGL((k_zderiv<Real, true>), grid, dim3(256), 0, s, f, static_cast<Real*>(dz),
-                       p, k0, k1, kchunk);
-  else
-    hipLaunchKernelGGL((k_zderiv<Real, false>), grid, dim3(256), 0, s, f, static_cast<Real*>(dz),
-                       p, k0, k1, kchunk);
-  return hipGetLastError();
-}
-
 template <typename Real, bool SOLAR, bool NEWTON>
 hipError_t launch_typed(const KParams& p, int stage, const double* f, const void* dzv,
                         double* fo, double* dF, const double* uh, const double* ah, StageArgs st,
@@ -585,11 +523,6 @@ hipError_t launch_prec(const KParams& p, int stage, const double* f, const void*
 
 }  // namespace
 
-size_t zderiv_bytes(const KParams& p, int prec) {
-  const size_t el = prec == CMHD_FP32_SPLIT ? sizeof(float) : sizeof(double);
-  return size_t(NZSLOT) * size_t(p.nz) * size_t(p.splane) * el;
-}
-
 ChunkPlan plan_chunks(const KParams& p) {
   ChunkPlan c;
   const int tiles = (p.nx / TX) * (p.ny / TY);
@@ -609,12 +542,6 @@ ChunkPlan plan_chunks(const KParams& p) {
     c.pipelined = false;
   }
   return c;
-}
-
-hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, int k0, int k1,
-                         hipStream_t s) {
-  return prec == CMHD_FP32_SPLIT ? launch_zderiv_typed<float>(p, f, dz, k0, k1, s)
-                                 : launch_zderiv_typed<double>(p, f, dz, k0, k1, s);
 }
 
 hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, const void* dz,
