@@ -8,15 +8,15 @@
 //   Zs  d/dz of A, u, ln T on the same haloed plane (for the xz, yz mixed
 //       derivatives D1_x D1_z, D1_y D1_z)
 //   Zo  d/dz ln rho and the 8 d2/dz2 at the own columns
-//   DF  the RK register at the own columns (substages 2 and 3)
 // each split into the fields of A and the others (separate LDS objects, so
 // that the compiler can tell a read of one from a copy in flight into the
-// other).  Per plane:
+// other).  The RK register of the own column (substages 2 and 3) is loaded
+// into registers at the top of each plane and used at its end.  Per plane:
 //   1a  stencils -> the pointwise inputs of all fields but A in registers;
 //       D1_x of the six fields with an xy mixed derivative on the tile and its
 //       y halo -> LDS
-//   --  barrier; copies of the RK register of plane k and of the non-A fields
-//       of plane k+1 are issued (their arrays were last read in 1a)
+//   --  barrier; copies of the non-A fields of plane k+1 are issued (their
+//       arrays were last read in 1a)
 //   1b  xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
 //   2a  radiative loss (table in LDS) and the magnetic part of the right-hand
 //       side, A's derivatives read from LDS on demand
@@ -139,7 +139,7 @@ template <typename Real>
 struct Copier {
   using CD = Chunks<8>;
   using CR = Chunks<sizeof(Real)>;
-  unsigned hd[2], hr[2], od, orl;
+  unsigned hd[2], hr[2], orl;
   int w, lane;
   __device__ void init(int w_, int lane_, int x0, int y0, int nx, int ny) {
     w = w_;
@@ -148,7 +148,6 @@ struct Copier {
     hd[1] = CD::halo(w + 4, lane, x0, y0, nx, ny);
     hr[0] = CR::halo(w, lane, x0, y0, nx, ny);
     hr[1] = CR::halo(w + 4, lane, x0, y0, nx, ny);
-    od = CD::own(w, lane, x0, y0, nx);
     orl = CR::own(w, lane, x0, y0, nx);
   }
   template <int E>
@@ -285,7 +284,6 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
   __shared__ __align__(16) Real sOA[NA][NT];      // d2/dz2 of A, own
   __shared__ __align__(16) Real sON[NON][NT];     // d/dz ln rho, d2/dz2 of the others, own
   __shared__ __align__(16) double sDx[NDX][DXP];  // D1_x (unscaled) on tile + y halo
-  __shared__ __align__(16) double sDF[NF][NT];    // RK register, own
   __shared__ __align__(16) double sRad[3 * CMHD_MAX_RAD];
   // Newtonian cooling profiles (only the NEWTON variant has the term)
   __shared__ __align__(16) double sNC[NEWTON ? 2 * CMHD_MAX_NC_TABLE : 1];
@@ -346,6 +344,13 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
   copies_barrier();
 
   for (int k = kbeg; k < kend; ++k) {
+    // the RK register of the own column, loaded at the top of the plane and
+    // consumed by the update at its end (registers, no LDS staging)
+    double dfr[NF];
+    if (READ_DF) {
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) dfr[fi] = dF[fi * sf + (k + NG) * sp + oc];
+    }
     // ---- 1a: stencils of the staged plane into registers (all but the
     // derivatives of A); D1_x of the xy-mixed fields into LDS
     const int ic = opaque(c - PC), icx = opaque(cx - DC), it = opaque(tid);
@@ -396,12 +401,8 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     }
     lds_barrier();
 
-    // ---- copies into the arrays last read in 1a: the RK register of this
-    // plane and the non-A fields of the next plane
-    if (READ_DF) {
-#pragma unroll
-      for (int fi = 0; fi < NF; ++fi) cp.template own<8>(dF + fi * sf + (k + NG) * sp, sDF[fi], cp.od);
-    }
+    // ---- copies into the arrays last read in 1a: the non-A fields of the
+    // next plane
     if (k + 1 < kend) copy_plane(k + 1, false);
 
     // ---- 1b: xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     for (int fi = 0; fi < NF; ++fi) {
       const long long pl = fi * sf + (k + NG) * sp;   // uniform
       const double r = double(out[fi]);
-      double d = READ_DF ? st.alpha * sDF[fi][tid] + st.dt * r : st.dt * r;
+      double d = READ_DF ? st.alpha * dfr[fi] + st.dt * r : st.dt * r;
       double fn = v64[fi] + st.beta * d;
       if (SOLAR) {
         // closed boundary (u_z = 0 at both boundary planes) and the
