@@ -107,33 +107,53 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // transform b: elements at base(b) + j*stride, j = 0..n-1, where
-// base(b) = (b / inner) * outer + (b % inner) * istride
-__global__ void k_fft1d(double2* __restrict__ data, int n, int logn, long long stride, int inner,
-                        long long outer, long long istride, double sign) {
+// base(b) = (b / inner) * outer + (b % inner) * istride.  One thread per
+// element (blockDim.x = n <= 1024), radix-2 decimation in time on the
+// bit-reversed input: thread t holds element t of the current stage.  A
+// butterfly's partner t ^ half lies in the same wavefront for half < 64 and
+// is exchanged with a lane shuffle; the longer stages exchange through LDS.
+// The twiddles exp(sign 2 pi i k / n), k < n/2, are evaluated once per block
+// into LDS (the stage of length len uses k = pos n / len).
+__global__ __launch_bounds__(1024) void k_fft1d(double2* __restrict__ data, int n, int logn,
+                                                long long stride, int inner, long long outer,
+                                                long long istride, double sign) {
   __shared__ double2 buf[1024];
+  __shared__ double2 tw[512];
   const long long b = blockIdx.x;
   const long long base = (b / inner) * outer + (b % inner) * istride;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int r = (int)(__brev((unsigned)i) >> (32 - logn));
-    buf[r] = data[base + i * stride];
-  }
-  for (int len = 2; len <= n; len <<= 1) {
-    const int half = len >> 1;
-    __syncthreads();
-    for (int t = threadIdx.x; t < (n >> 1); t += blockDim.x) {
-      const int g = t / half, pos = t - g * half;
-      const int i0 = g * len + pos, i1 = i0 + half;
-      double sn, cs;
-      sincospi(2.0 * pos / len, &sn, &cs);
-      const double2 w = make_double2(cs, sign * sn);
-      const double2 a = buf[i0];
-      const double2 bb = cmul(buf[i1], w);
-      buf[i0] = make_double2(a.x + bb.x, a.y + bb.y);
-      buf[i1] = make_double2(a.x - bb.x, a.y - bb.y);
-    }
+  const int t = threadIdx.x;
+  const int r = (int)(__brev((unsigned)t) >> (32 - logn));
+  double2 v = data[base + r * stride];
+  if (t < n / 2) {
+    double sn, cs;
+    sincospi(2.0 * t / n, &sn, &cs);
+    tw[t] = make_double2(cs, sign * sn);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) data[base + i * stride] = buf[i];
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1;
+    double2 o;
+    if (half < 64) {
+      o.x = __shfl_xor(v.x, half);
+      o.y = __shfl_xor(v.y, half);
+    } else {
+      buf[t] = v;
+      __syncthreads();
+      o = buf[t ^ half];
+      __syncthreads();
+    }
+    const int pos = t & (half - 1);
+    const double2 w = tw[pos * (n / len)];
+    // lower element t: a + w b with b = o; upper element: a - w b with a = o, b = v
+    if ((t & half) == 0) {
+      const double2 bb = cmul(o, w);
+      v = make_double2(v.x + bb.x, v.y + bb.y);
+    } else {
+      const double2 bb = cmul(v, w);
+      v = make_double2(o.x - bb.x, o.y - bb.y);
+    }
+  }
+  data[base + t * stride] = v;
 }
 
 }  // namespace
@@ -142,13 +162,11 @@ __global__ void k_fft1d(double2* __restrict__ data, int n, int logn, long long s
 hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStream_t s) {
   const int nx = p.nx, ny = p.ny;
   const long long plane = (long long)nx * ny;
-  const int tx = nx / 2 < 256 ? nx / 2 : 256;
-  const int ty = ny / 2 < 256 ? ny / 2 : 256;
-  // rows: transform b = (plane, row); contiguous
-  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * ny), dim3(tx), 0, s, d, nx, ilog2(nx), 1LL, 1,
+  // rows: transform b = (plane, row); contiguous; one thread per element
+  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * ny), dim3(nx), 0, s, d, nx, ilog2(nx), 1LL, 1,
                      (long long)nx, 0LL, sign);
   // columns: transform b = (plane, column); stride nx
-  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * nx), dim3(ty), 0, s, d, ny, ilog2(ny),
+  hipLaunchKernelGGL(k_fft1d, dim3(nplanes * nx), dim3(ny), 0, s, d, ny, ilog2(ny),
                      (long long)nx, nx, plane, 1LL, sign);
   return hipGetLastError();
 }
