@@ -13,6 +13,7 @@ re-seeded every 10 steps (device-resident targets, set with cmhd_set_driver).
 Prints one JSON line: the FP64 throughput (zone-updates/s) as `value`, the
 FP32-split form beside it, the HBM roofline of the fused kernel from HIP
 events around its launches, the same box on a non-uniform z grid (FP64), the
+1024 x 1024 x 256 active-region box in the FP32-split form, the
 granulation driver's cost per snapshot on the same photospheric plane (outside
 the timed steps), and the CPU oracle timed on a bounded sample.
 """
@@ -219,6 +220,8 @@ def main():
     ap.add_argument("--no-driver", action="store_true", help="skip the granulation-driver timing")
     ap.add_argument("--no-stretched", action="store_true",
                     help="skip the same box on the non-uniform z grid")
+    ap.add_argument("--no-ar1024", action="store_true",
+                    help="skip the 1024x1024x256 active-region box (FP32-split)")
     ap.add_argument("--split-error-steps", type=int, default=100,
                     help="steps of the FP32-split vs FP64 error run (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -315,6 +318,20 @@ def main():
                               "value": rs["value"], "ms_per_step": rs["ms_per_step"],
                               "substage_ms": rs["substage_ms"], "roofline_frac": rs["frac"],
                               "steps": max(args.steps // 2, 1), "finite": rs["finite"]}
+    if not args.no_ar1024 and w.name == "strat512":
+        # the active-region box of the same physics, 1024 x 1024 x 256 over
+        # 64 Mm with 32 bipoles, in the FP32-split form
+        log("[bench] ar1024 fp32_split")
+        wa = W.ar1024()
+        ra = run_gpu(wa, "fp32_split", max(args.steps // 2, 1), args.warmup,
+                     [torch.as_tensor(W.driver_reseed(wa, 100 + k), device="cuda")
+                      for k in range(2)])
+        log(f"[bench] ar1024: {ra}")
+        out["ar1024"] = {"workload": "ar1024: 1024x1024x256 over 64 Mm, 32 bipoles, FP32-split",
+                         "value": ra["value"], "ms_per_step": ra["ms_per_step"],
+                         "substage_ms": ra["substage_ms"], "roofline_frac": ra["frac"],
+                         "steps": max(args.steps // 2, 1), "finite": ra["finite"]}
+        del wa
     if not args.no_driver and g["zbc"] == "solar":
         log("[bench] granulation driver")
         out["driver"] = driver_bench(w, r["dt"], r["ms_per_step"])
