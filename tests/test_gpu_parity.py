@@ -374,3 +374,43 @@ def test_ragged_z_chunks(nx, nz):
     print(f"[case] ragged z chunks {nx}x{nx}x{nz}", flush=True)
     assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
                   f"ragged {nx}x{nx}x{nz}")
+
+
+def _rhs_case(name):
+    if name == "newton":
+        return newton_case()
+    if name == "stretched":
+        return W.small_stretched(32, 32, 24)
+    return CASES[name]()
+
+
+@pytest.mark.parametrize("case,precision,t", [
+    ("periodic16", "fp64", 0.0), ("strat32x32x24", "fp64", 0.0), ("strat32x32x24", "fp64", 0.03),
+    ("strat32x32x24_norad", "fp64", 0.0), ("newton", "fp64", 0.0), ("stretched", "fp64", 0.0),
+    ("strat32x32x24", "fp32_split", 0.0)])
+def test_eval_rhs_matches_oracle(case, precision, t):
+    # cmhd_eval_rhs: dF/dt at every interior zone and at the u_x, u_y ghost
+    # rows (nudging alone there), against the oracle's right-hand side; t
+    # inside the switch-on ramp scales the nudging target
+    import torch
+    from paper_1908_08557_amd import cmhd
+    w = _rhs_case(case)
+    solar = w.grid["zbc"] == "solar"
+    if solar and t > 0.0:
+        w.params.update(t_ramp=0.06)
+    print(f"[case] eval_rhs {case} {precision} t={t}", flush=True)
+    F = O.from_compact(w.state)
+    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
+    drv = dict(uh=w.uh_target, ah=w.ah_target) if solar else None
+    R, Rgh = O.rhs(F, t, w.grid, w.params, drv)
+    ref = np.zeros_like(w.state)
+    ref[:, NG:-NG] = R
+    if solar:
+        ref[3:5, :NG] = Rgh
+    s = cmhd.solver_for(w, precision)
+    got = s.eval_rhs(s.new_state(w.state), t)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    s.close()
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    assert_parity(got, ref, solar, tol, f"eval_rhs {case} {precision} t={t}")
