@@ -193,8 +193,7 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
 }
 
 // optically thin loss Q_rad/(rho c_v T) = exp(ln rho + lnL(ln T) - ln T) W(ln T) / c_v
-// (the only table lookup of the right-hand side; a kernel may evaluate it
-// early, before it starts memory traffic that the lookup must not wait on)
+// (the only table lookup of the right-hand side)
 template <typename S, class Src, class Tab>
 __device__ __forceinline__ S rhs_radiation(const Src& src, const KParams& p, const Tab& tab) {
   constexpr bool kFloat = std::is_same<S, float>::value;

@@ -17,11 +17,13 @@
 //       y halo -> LDS
 //   --  barrier; copies of the non-A fields of plane k+1 are issued (their
 //       arrays were last read in 1a)
-//   1b  xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
-//   2a  radiative loss (table in LDS) and the magnetic part of the right-hand
-//       side, A's derivatives read from LDS on demand
+//   2a  the magnetic part of the right-hand side, A's derivatives read from
+//       LDS on demand
 //   --  barrier; copies of the A fields of plane k+1 are issued
-//   2b  fluid part of the right-hand side from registers
+//   2b  xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T (from the D1_x
+//       array, which no copy writes), radiative loss (table in LDS) and the
+//       fluid part of the right-hand side from registers: the work that
+//       needs no staged plane, placed where it overlaps the A copies
 //   --  wait for the copies, barrier
 //   3   dF <- alpha dF + dt RHS, f_next <- f + beta dF in float64, stored once
 // The arithmetic of every derivative is that of the product stencils applied
@@ -405,13 +407,9 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
     // next plane
     if (k + 1 < kend) copy_plane(k + 1, false);
 
-    // ---- 1b: xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T
     const double ixy = p.i60dx * p.i60dy;
-#pragma unroll
-    for (int fi = UX; fi < NF; ++fi)
-      if (dx_index(fi) >= 0) q[q_h(fi, 3)] = Real(d1u(pDx, dx_index(fi) * DXP + DC, DXW) * ixy);
 
-    // ---- 2a: radiative loss and the magnetic part (A read from LDS)
+    // ---- 2a: the magnetic part (A read from LDS)
     PointCtx<Real> pc;
     swamp(p, k, pc.w, pc.dw);
     pc.bottom = SOLAR && k == 0;
@@ -431,15 +429,19 @@ __global__ __launch_bounds__(NT) void k_rhs_rk(const double* __restrict__ f,
                                  p.i60dx, p.i60dy, p.i180dx2, p.i180dy2, ixy};
     Real out[NF];
     MagState<Real> mag;
-    const Real rad = rhs_radiation<Real>(src, p, LdsRadTable{sRad});
-    const Real nc = NEWTON ? rhs_newton<Real>(src, p, LdsNcTable{sNC, p.nc_n}, pc) : Real(0.0);
     rhs_magnetic<Real>(src, pc, p, out, mag);
     lds_barrier();
 
     // ---- copies of the A fields of the next plane
     if (k + 1 < kend) copy_plane(k + 1, true);
 
-    // ---- 2b: fluid part of the right-hand side, from registers
+    // ---- 2b: xy mixed derivatives D1_y (D1_x f) of u_x, u_y, ln T, radiative
+    // loss and the fluid part of the right-hand side, while the copies land
+#pragma unroll
+    for (int fi = UX; fi < NF; ++fi)
+      if (dx_index(fi) >= 0) q[q_h(fi, 3)] = Real(d1u(pDx, dx_index(fi) * DXP + DC, DXW) * ixy);
+    const Real rad = rhs_radiation<Real>(src, p, LdsRadTable{sRad});
+    const Real nc = NEWTON ? rhs_newton<Real>(src, p, LdsNcTable{sNC, p.nc_n}, pc) : Real(0.0);
     rhs_fluid<Real>(src, pc, p, mag, rad, nc, out);
 
     copies_barrier();

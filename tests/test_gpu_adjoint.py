@@ -219,3 +219,38 @@ def test_adjoint128_gradient_at_10mm():
     w = W2.adjoint128()
     target = torch.as_tensor(w.extra["bz_target_z10"], device="cuda")
     assert _gradient_and_fd(10.0, target, 1e-2, 8) <= 1e-3
+
+
+@pytest.mark.parametrize("grid", ["uniform", "stretched"])
+def test_bz_plane_vjp_dot_product(grid):
+    # B_z on a plane is affine in the state: <bz(x + dx) - bz(x), bzbar> must
+    # equal <dx, vjp(bzbar)> at heights on a plane, between planes and at the
+    # top plane, and the call adds into xbar (a second call doubles it)
+    import torch
+    w = (W.small_stratified(32, 32, 16, Lxy=12.0, z1=12.0, nbip=2) if grid == "uniform"
+         else W.small_stretched(32, 32, 16, Lxy=12.0, nbip=2))
+    print(f"[case] bz_plane_vjp dot product ({grid} z)", flush=True)
+    s = _solver(w)
+    x = s.new_state(w.state)
+    d = _random_direction(w, 3)
+    dx = torch.as_tensor(d, device="cuda")
+    rng = np.random.default_rng(5)
+    z = O.zk(w.grid)
+    nz = w.grid["nz"]
+    for zq in (z[NG + 4], 0.35 * z[NG + 6] + 0.65 * z[NG + 7], z[NG + nz - 1]):
+        bzbar = torch.as_tensor(rng.standard_normal((w.grid["ny"], w.grid["nx"])), device="cuda")
+        lhs = float(((s.bz_plane(x + dx, zq) - s.bz_plane(x, zq)) * bzbar).sum())
+        xbar = torch.zeros_like(x)
+        s.bz_plane_vjp(zq, bzbar, xbar)
+        rhs = float((dx * xbar).sum())
+        rel = abs(lhs - rhs) / abs(lhs)
+        print(f"[adj] z={zq:.4f}: <L dx, b> {lhs:.15e} <dx, L^T b> {rhs:.15e} rel {rel:.2e}",
+              flush=True)
+        assert rel <= 1e-12
+        # only A_x, A_y enter B_z
+        assert float(xbar[2:].abs().max()) == 0.0
+        once = xbar.clone()
+        s.bz_plane_vjp(zq, bzbar, xbar)
+        torch.cuda.synchronize()
+        assert torch.equal(xbar, 2 * once)
+    s.close()
