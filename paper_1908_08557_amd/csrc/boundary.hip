@@ -313,31 +313,22 @@ __device__ double d1xy(const KParams& p, const double* f, int fi, int kz, long l
   return acc * (axis == 0 ? p.i60dx : p.i60dy);
 }
 
+// One block per (y, z) row of the interior, threads along x: the periodic
+// neighbours are found by comparison, with no integer division per zone.
 __global__ void k_cfl(const KParams p, const double* __restrict__ f,
                       unsigned long long* __restrict__ out3) {
   __shared__ double red[3][256];
   double ms = 0.0, md = 0.0, mr = 0.0;
-  const long long n = (long long)p.nz * p.splane;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int k = int(i / p.splane);
-    const long long col = i - (long long)k * p.splane;
+  const long long nrows = (long long)p.nz * p.ny;
+  for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int k = int(row / p.ny), y = int(row - (long long)k * p.ny);
     const int kz = k + NG;
-    const long long o = (long long)kz * p.splane + col;
-    const double dAz_dy = d1xy(p, f, AZ, kz, col, 1), dAz_dx = d1xy(p, f, AZ, kz, col, 0);
-    const double dAy_dx = d1xy(p, f, AY, kz, col, 0), dAx_dy = d1xy(p, f, AX, kz, col, 1);
+    const long long pl = (long long)kz * p.splane;
+    auto wy = [&](int d) { return y + d < 0 ? y + d + p.ny : (y + d >= p.ny ? y + d - p.ny : y + d); };
+    const long long ym1 = (long long)wy(-1) * p.nx, ym2 = (long long)wy(-2) * p.nx,
+                    ym3 = (long long)wy(-3) * p.nx, yp1 = (long long)wy(1) * p.nx,
+                    yp2 = (long long)wy(2) * p.nx, yp3 = (long long)wy(3) * p.nx;
     const double mz = p.stretched ? p.ztab[zt_c1(p) + k] : p.i60dz;
-    const double dAy_dz = d1col(f + AY * p.sfield + o, p.splane) * mz;
-    const double dAx_dz = d1col(f + AX * p.sfield + o, p.splane) * mz;
-    const double Bx = dAz_dy - dAy_dz + p.Bext[0];
-    const double By = dAx_dz - dAz_dx + p.Bext[1];
-    const double Bz = dAy_dx - dAx_dy + p.Bext[2];
-    const double ux = f[UX * p.sfield + o], uy = f[UY * p.sfield + o], uz = f[UZ * p.sfield + o];
-    const double lr = f[LR * p.sfield + o], lT = f[LT * p.sfield + o];
-    const double rho = exp(lr), T = exp(lT);
-    const double B2 = Bx * Bx + By * By + Bz * Bz;
-    const double cf = sqrt(p.gamma * p.R * T + B2 / (p.mu0 * rho));
-    double spd = sqrt(ux * ux + uy * uy + uz * uz) + cf;
     double w = 0.0;
     if (p.solar) {
       const double z = zk(p, k);
@@ -345,39 +336,66 @@ __global__ void k_cfl(const KParams p, const double* __restrict__ f,
       s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
       w = s * s * (3.0 - 2.0 * s);
     }
-    double D = p.nu;
-    D = fmax(D, p.eta + p.eta_s * w);
-    D = fmax(D, p.D_rho + p.chi_rho * w);
-    D = fmax(D, p.chi_s * w);
-    D = fmax(D, p.kappa0 * exp(2.5 * lT) / (rho * p.cv));
-    if (p.stretched) {
-      // non-uniform grid: rates per unit of the plane's own spacing
-      const double dl = fmin(p.dxy_min, p.ztab[zt_zp(p) + k]);
-      spd = spd / dl;
-      D = D / (dl * dl);
-    }
-    double rate = 0.0;
-    if (p.n_rad > 0 && lT > p.lnT_rad_lo) {
-      int seg = 0;
-      for (int j = 1; j < p.n_rad - 1; ++j) seg = (lT >= p.rad_lnT[j]) ? j : seg;
-      double lnL;
-      if (lT < p.rad_lnT[0])
-        lnL = p.rad_lnL[0];
-      else if (lT >= p.rad_lnT[p.n_rad - 1])
-        lnL = p.rad_lnL[p.n_rad - 1];
-      else
-        lnL = p.rad_lnL[seg] + p.rad_slope[seg] * (lT - p.rad_lnT[seg]);
-      double wc = 1.0;
-      if (lT < p.lnT_rad_hi) {
-        const double s = (lT - p.lnT_rad_lo) * p.inv_dlnT_rad;
-        wc = s * s * (3.0 - 2.0 * s);
+    const double dl = p.stretched ? fmin(p.dxy_min, p.ztab[zt_zp(p) + k]) : 1.0;
+    for (int x = threadIdx.x; x < p.nx; x += blockDim.x) {
+      const long long o = pl + (long long)y * p.nx + x;
+      // x and y first derivatives by the sixth-order stencil, wrapped
+      auto wx = [&](int d) { return x + d < 0 ? x + d + p.nx : (x + d >= p.nx ? x + d - p.nx : x + d); };
+      const int xm1 = wx(-1), xm2 = wx(-2), xm3 = wx(-3), xp1 = wx(1), xp2 = wx(2), xp3 = wx(3);
+      auto dx = [&](int fi) {
+        const double* a = f + fi * p.sfield + pl + (long long)y * p.nx;
+        return (45.0 * (a[xp1] - a[xm1]) - 9.0 * (a[xp2] - a[xm2]) + (a[xp3] - a[xm3])) * p.i60dx;
+      };
+      auto dy = [&](int fi) {
+        const double* a = f + fi * p.sfield + pl + x;
+        return (45.0 * (a[yp1] - a[ym1]) - 9.0 * (a[yp2] - a[ym2]) + (a[yp3] - a[ym3])) * p.i60dy;
+      };
+      const double dAz_dy = dy(AZ), dAz_dx = dx(AZ);
+      const double dAy_dx = dx(AY), dAx_dy = dy(AX);
+      const double dAy_dz = d1col(f + AY * p.sfield + o, p.splane) * mz;
+      const double dAx_dz = d1col(f + AX * p.sfield + o, p.splane) * mz;
+      const double Bx = dAz_dy - dAy_dz + p.Bext[0];
+      const double By = dAx_dz - dAz_dx + p.Bext[1];
+      const double Bz = dAy_dx - dAx_dy + p.Bext[2];
+      const double ux = f[UX * p.sfield + o], uy = f[UY * p.sfield + o], uz = f[UZ * p.sfield + o];
+      const double lr = f[LR * p.sfield + o], lT = f[LT * p.sfield + o];
+      const double rho = exp(lr), T = exp(lT);
+      const double B2 = Bx * Bx + By * By + Bz * Bz;
+      const double cf = sqrt(p.gamma * p.R * T + B2 / (p.mu0 * rho));
+      double spd = sqrt(ux * ux + uy * uy + uz * uz) + cf;
+      double D = p.nu;
+      D = fmax(D, p.eta + p.eta_s * w);
+      D = fmax(D, p.D_rho + p.chi_rho * w);
+      D = fmax(D, p.chi_s * w);
+      D = fmax(D, p.kappa0 * exp(2.5 * lT) / (rho * p.cv));
+      if (p.stretched) {
+        // non-uniform grid: rates per unit of the plane's own spacing
+        spd = spd / dl;
+        D = D / (dl * dl);
       }
-      rate = exp(lr + lnL - lT) * wc / p.cv;   // Q_rad / (rho c_v T)
+      double rate = 0.0;
+      if (p.n_rad > 0 && lT > p.lnT_rad_lo) {
+        int seg = 0;
+        for (int j = 1; j < p.n_rad - 1; ++j) seg = (lT >= p.rad_lnT[j]) ? j : seg;
+        double lnL;
+        if (lT < p.rad_lnT[0])
+          lnL = p.rad_lnL[0];
+        else if (lT >= p.rad_lnT[p.n_rad - 1])
+          lnL = p.rad_lnL[p.n_rad - 1];
+        else
+          lnL = p.rad_lnL[seg] + p.rad_slope[seg] * (lT - p.rad_lnT[seg]);
+        double wc = 1.0;
+        if (lT < p.lnT_rad_hi) {
+          const double s = (lT - p.lnT_rad_lo) * p.inv_dlnT_rad;
+          wc = s * s * (3.0 - 2.0 * s);
+        }
+        rate = exp(lr + lnL - lT) * wc / p.cv;   // Q_rad / (rho c_v T)
+      }
+      // NaN propagates: fmax would drop it, so test explicitly
+      ms = (spd > ms || spd != spd) ? spd : ms;
+      md = (D > md || D != D) ? D : md;
+      mr = (rate > mr || rate != rate) ? rate : mr;
     }
-    // NaN propagates: fmax would drop it, so test explicitly
-    ms = (spd > ms || spd != spd) ? spd : ms;
-    md = (D > md || D != D) ? D : md;
-    mr = (rate > mr || rate != rate) ? rate : mr;
   }
   red[0][threadIdx.x] = ms;
   red[1][threadIdx.x] = md;
@@ -510,7 +528,8 @@ hipError_t launch_ah_from_bz(const KParams& p, const double* bz, double* ah, dou
 hipError_t launch_cfl_max(const KParams& p, const double* f, unsigned long long* out3,
                           hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out3, 3);
-  hipLaunchKernelGGL(k_cfl, dim3(grid_for((long long)p.nz * p.splane)), dim3(256), 0, s, p, f,
+  const long long rows = (long long)p.nz * p.ny;
+  hipLaunchKernelGGL(k_cfl, dim3(unsigned(rows < 65536 ? rows : 65536)), dim3(256), 0, s, p, f,
                      out3);
   return hipGetLastError();
 }
