@@ -12,7 +12,8 @@ re-seeded every 10 steps (device-resident targets, set with cmhd_set_driver).
 
 Prints one JSON line: the FP64 throughput (zone-updates/s) as `value`, the
 FP32-split form beside it, the HBM roofline of the fused kernel from HIP
-events around its launches, the same box on a non-uniform z grid (FP64), the
+events around its launches (with the rate of a plain device copy measured in
+the same run, the counters' HBM traffic and VALU busy), the same box on a non-uniform z grid (FP64), the
 1024 x 1024 x 256 active-region box in the FP32-split form, the
 granulation driver's cost per snapshot on the same photospheric plane (outside
 the timed steps), and the CPU oracle timed on a bounded sample.
@@ -41,6 +42,26 @@ METRIC = ("zone-updates/s per RK3 step (FP64 vs FP32-split) + % HBM roofline, "
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth(mib=2048, reps=10):
+    """GB/s (bytes read + written) of a device-to-device copy of `mib` MiB,
+    timed with HIP events on the current stream."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def measured_traffic():
@@ -298,6 +319,11 @@ def main():
             log(f"[bench] split error: {e}")
             out["fp32_split"]["rel_err_vs_fp64"] = e
             out["fp32_split"]["rel_err_steps"] = args.split_error_steps
+    # the HBM rate a plain device copy reaches on this GPU (read + write), the
+    # practical ceiling beside the published peak
+    cbw = copy_bandwidth()
+    out["roofline"]["copy_GBs"] = cbw
+    out["roofline"]["frac_of_copy"] = r["achieved_GBs"] / cbw
     tr = measured_traffic() if (w.name == "strat512" and main_prec == "fp64") else None
     if tr is not None:
         out["roofline"]["traffic"] = tr["hbm_bytes_per_substage"]
