@@ -72,11 +72,12 @@ def test_strat512_one_step_sampled(precision, tol):
 
 
 @pytest.mark.timeout(900)
-def test_strat512_stretched_one_step_sampled():
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_split", 2e-6)])
+def test_strat512_stretched_one_step_sampled(precision, tol):
     w = W.strat512_stretched()
-    print(f"[case] strat512_stretched one step fp64, {NSAMPLE} sampled zones", flush=True)
-    got, dt = _gpu_one_step(w, "fp64")
-    _check(w, got, dt, 1e-12, "strat512_stretched fp64")
+    print(f"[case] strat512_stretched one step {precision}, {NSAMPLE} sampled zones", flush=True)
+    got, dt = _gpu_one_step(w, precision)
+    _check(w, got, dt, tol, f"strat512_stretched {precision}")
 
 
 @pytest.mark.timeout(1200)
