@@ -13,7 +13,8 @@ re-seeded every 10 steps (device-resident targets, set with cmhd_set_driver).
 Prints one JSON line: the FP64 throughput (zone-updates/s) as `value`, the
 FP32-split form beside it, the HBM roofline of the fused kernel from HIP
 events around its launches (with the rate of a plain device copy measured in
-the same run, the counters' HBM traffic and VALU busy), the same box on a non-uniform z grid (FP64), the
+the same run, the counters' HBM traffic and VALU busy), 32^2 x 24 and 64^3 boxes
+stepped eagerly and from a captured HIP graph, the same box on a non-uniform z grid (FP64), the
 1024 x 1024 x 256 active-region box in the FP32-split form, the
 granulation driver's cost per snapshot on the same photospheric plane (outside
 the timed steps), and the CPU oracle timed on a bounded sample.
@@ -124,6 +125,47 @@ def run_gpu(w, precision, steps, warmup, drivers):
                 zderiv_ms_per_launch=zderiv_ms_per_launch, substage_ms=substage_ms,
                 achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS,
                 step_GBs=BYTES_PER_ZONE_STEP * zones / (elapsed / steps) / 1e9)
+
+
+def graph_bench(n=64, nz=64, nsteps=10, reps=5):
+    """A small stratified box (each step is some 60 small launches) stepped
+    eagerly and as replays of one captured HIP graph of nsteps steps (dt
+    fixed, ramp off, so the steps are time-independent)."""
+    import torch
+    from paper_1908_08557_amd import cmhd
+    from paper_1908_08557_amd import workloads as W
+    w = W.stratified_box(n, n, nz, 50.0 * n / 64, 50.0 * nz / 64, 8, 2, 3, f"strat{n}", t_ramp=0.0)
+    s = cmhd.solver_for(w)
+    x = s.new_state(w.state)
+    dt = s.cfl_dt(x)
+    for _ in range(3):
+        s.rk3_step(x, 0.0, dt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(nsteps * reps):
+        s.rk3_step(x, 0.0, dt)
+    e1.record()
+    torch.cuda.synchronize()
+    eager = e0.elapsed_time(e1) / (nsteps * reps)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(nsteps):
+            s.rk3_step(x, 0.0, dt)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph = e0.elapsed_time(e1) / (nsteps * reps)
+    finite = bool(torch.isfinite(x).all())
+    del g
+    s.close()
+    return {"workload": f"{n}x{n}x{nz} stratified box, FP64, ramp off", "eager_ms_per_step": eager,
+            "graph_ms_per_step": graph, "speedup": eager / graph,
+            "steps_per_graph": nsteps, "finite": finite}
 
 
 def driver_bench(w, dt, ms_per_step, reps=5):
@@ -241,6 +283,8 @@ def main():
     ap.add_argument("--no-driver", action="store_true", help="skip the granulation-driver timing")
     ap.add_argument("--no-stretched", action="store_true",
                     help="skip the same box on the non-uniform z grid")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the eager vs HIP-graph timing of the small boxes")
     ap.add_argument("--no-ar1024", action="store_true",
                     help="skip the 1024x1024x256 active-region box (FP32-split)")
     ap.add_argument("--split-error-steps", type=int, default=100,
@@ -358,6 +402,10 @@ def main():
                          "substage_ms": ra["substage_ms"], "roofline_frac": ra["frac"],
                          "steps": max(args.steps // 2, 1), "finite": ra["finite"]}
         del wa
+    if not args.no_graph:
+        log("[bench] small boxes, eager vs HIP graph")
+        out["graph"] = [graph_bench(32, 24), graph_bench(64, 64)]
+        log(f"[bench] graph: {out['graph']}")
     if not args.no_driver and g["zbc"] == "solar":
         log("[bench] granulation driver")
         out["driver"] = driver_bench(w, r["dt"], r["ms_per_step"])
