@@ -293,7 +293,7 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of the build)", file=sys.stderr)
         sys.exit(2)
 
