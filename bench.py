@@ -97,13 +97,20 @@ def run_gpu(w, precision, steps, warmup, drivers):
     s.profile_read("substage")
     s.profile_read("zderiv")
     torch.cuda.synchronize()
+    # events at the thirds of the timed region (no synchronisation inside it)
+    marks = sorted({0, steps // 3, (2 * steps) // 3, steps})
+    evs = {m: torch.cuda.Event(enable_timing=True) for m in marks}
     t0 = time.perf_counter()
     for i in range(steps):
+        if i in evs:
+            evs[i].record()
         if i % 10 == 0:
             s.set_driver(drivers[(i // 10) % len(drivers)])
         t, _ = s.rk3_step(st, t, dt)
+    evs[steps].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    blocks = [evs[a].elapsed_time(evs[b]) / (b - a) for a, b in zip(marks[:-1], marks[1:])]
     kms, nl = s.profile_read("substage")
     zms, nz_ = s.profile_read("zderiv")
     s.profile(False)
@@ -121,6 +128,7 @@ def run_gpu(w, precision, steps, warmup, drivers):
     alg_bytes_launch = BYTES_PER_ZONE_STEP / 3.0 * zones
     achieved = alg_bytes_launch / (substage_ms * 1e-3) / 1e9
     return dict(value=zones / (elapsed / steps), ms_per_step=ms_step, dt=dt, finite=finite,
+                ms_per_step_blocks=blocks, ms_per_step_median_block=float(np.median(blocks)),
                 kernel_ms_per_launch=kernel_ms_per_launch, launches=nl,
                 zderiv_ms_per_launch=zderiv_ms_per_launch, substage_ms=substage_ms,
                 achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS,
@@ -333,6 +341,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"],
+        "ms_per_step_blocks": r["ms_per_step_blocks"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
