@@ -282,15 +282,16 @@ cmhd_status cmhd_rk3_step_vjp(cmhd_ctx* ctx, double* x, double t, double dt, con
 cmhd_status cmhd_bz_plane_vjp(cmhd_ctx* ctx, double z, const double* bzbar, double* xbar);
 
 /* Kernel timing.  While enabled, every substage (cmhd_rk3_step,
- * cmhd_eval_rhs and the forward recomputation of the adjoint) records a pair
- * of HIP events on the context stream around each launch of the two kernels
- * selected by cmhd_prof_kernel: the fused stencil/RHS/RK kernel and the
- * z-derivative pass that precedes it.  cmhd_profile_read synchronises the
- * stream, returns for the selected kernel the summed duration in milliseconds
- * and the number of launches since its last read, and resets them; an
- * unknown selector is CMHD_EINVAL.  Enabling and disabling keep pending
- * records. */
-typedef enum { CMHD_PROF_SUBSTAGE = 0, CMHD_PROF_ZDERIV = 1 } cmhd_prof_kernel;
+ * cmhd_eval_rhs and the forward recomputation of the adjoint) records pairs
+ * of HIP events on the context stream around its two parts, selected by
+ * cmhd_prof_kernel: the fused stencil/RHS/RK kernel (CMHD_PROF_SUBSTAGE) and
+ * the boundary work that precedes it (CMHD_PROF_GHOSTS: ghost fill with the
+ * Fourier filters, driver target, nudged ghost rows).  cmhd_profile_read
+ * synchronises the stream, returns for the selected part the summed duration
+ * in milliseconds and the number of timed regions since its last read, and
+ * resets them; an unknown selector is CMHD_EINVAL.  Enabling and disabling
+ * keep pending records. */
+typedef enum { CMHD_PROF_SUBSTAGE = 0, CMHD_PROF_GHOSTS = 1 } cmhd_prof_kernel;
 cmhd_status cmhd_profile_enable(cmhd_ctx* ctx, int enable);
 cmhd_status cmhd_profile_read(cmhd_ctx* ctx, int which, double* ms, int* launches);
 

@@ -30,13 +30,50 @@ FLAGS = [
 ]
 
 
-# per-source extra flags.  The fused substage kernel is latency-bound at one
-# wave per SIMD; the iterative ILP scheduling strategy orders its plane loop
-# for more overlap (4-5% faster per substage at 512^2 x 256, measured), while
-# it slows the streaming z-derivative pass, which keeps the default.
+# per-source extra flags.  The fused substage kernel runs 16 waves per CU at
+# 128 registers each: machine loop-invariant code motion would hoist the
+# float64 constants of exp() and other loop-invariant values out of the plane
+# loop into registers, which this register budget cannot hold.
 SOURCE_FLAGS = {
-    "rhs_rk.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "substage.hip": ["-mllvm", "-disable-machine-licm"],
 }
+
+
+# Kernels that must run without scratch memory: their register budget is
+# exact (16 waves per CU at 128 registers), and builds of the fused substage
+# kernel that spilled to scratch gave wrong Runge-Kutta substages 2-3.  The
+# build fails if the compiler places any scratch access in them.
+NO_SCRATCH = {"substage.hip": "k_substage"}
+
+
+def scratch_report(src: str, kernel_substr: str, extra_flags=()) -> dict:
+    """Scratch load/store instruction count of every kernel of `src` whose
+    name contains `kernel_substr`, from the device assembly of this build."""
+    import re
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "k.s")
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), *extra_flags,
+               "--cuda-device-only", "-S", src, "-o", out]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc -S failed for {src}:\n{r.stderr}")
+        text = open(out).read()
+    counts = {}
+    for m in re.finditer(r"^(\S*" + re.escape(kernel_substr) + r"\S*):", text, re.M):
+        end = text.index("s_endpgm", m.end())
+        counts[m.group(1)] = len(re.findall(r"\bscratch_(?:load|store)", text[m.end():end]))
+    return counts
+
+
+def check_no_scratch(extra_flags=()) -> None:
+    for name, kern in NO_SCRATCH.items():
+        counts = scratch_report(os.path.join(CSRC, name), kern, extra_flags)
+        if not counts:
+            raise RuntimeError(f"no {kern} kernel found in {name}")
+        bad = {k: n for k, n in counts.items() if n}
+        if bad:
+            raise RuntimeError(f"{name}: kernels with scratch accesses: {bad}")
 
 
 def sources():
@@ -62,6 +99,8 @@ def build(verbose: bool = False, extra_flags=()) -> str:
 
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(compile_one, sources()))
+        guard = ex.submit(check_no_scratch, extra_flags)
+        guard.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

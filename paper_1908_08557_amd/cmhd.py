@@ -366,8 +366,8 @@ class Solver:
 
     def profile_read(self, which="substage"):
         """(total ms, launches) since the last read of the fused substage
-        kernel ("substage") or of the z-derivative pass ("zderiv")."""
-        sel = {"substage": 0, "zderiv": 1}[which]
+        kernel ("substage") or of the boundary work before it ("ghosts")."""
+        sel = {"substage": 0, "ghosts": 1}[which]
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int(0)
         self._check(self.lib.cmhd_profile_read(self.ctx, sel, ctypes.byref(ms), ctypes.byref(n)))

@@ -30,17 +30,12 @@ struct cmhd_ctx {
   double* ah = nullptr;   // A_h* target    [2][ny][nx]
   double2* fft = nullptr; // Fourier scratch
   unsigned long long* red = nullptr;  // reduction scratch
-  void* dz = nullptr;     // z derivatives of the substage input [16][nz][ny][nx]
   std::vector<double> nc_host;   // initial [ln rho0 | ln T0] profiles (Newtonian cooling)
   double* nc_dev = nullptr;      // their device copy in the workspace
   std::vector<double> z_host;    // plane heights z_k, k = -3..nz+2
   std::vector<double> zt_host;   // the z table of KParams::ztab (non-uniform grids)
   double* zt_dev = nullptr;
-  // second stream for the z-derivative pass of the pipelined substage, and
-  // the events that order it against the caller's stream (created at init)
-  hipStream_t zs = nullptr;
-  hipEvent_t ev_fork = nullptr;
-  std::vector<hipEvent_t> ev_z;
+  KParams* kp_dev = nullptr;     // device copy of kp (read by the fused substage kernel)
   std::string err;
   // adjoint workspace
   char* aws = nullptr;
@@ -49,9 +44,6 @@ struct cmhd_ctx {
   // per timed kernel (CMHD_PROF_*): event pairs recorded and not yet read
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[2], ev_free;
   ~cmhd_ctx() {
-    for (auto& e : ev_z) (void)hipEventDestroy(e);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (zs) (void)hipStreamDestroy(zs);
     for (auto& v : ev_pending)
       for (auto& e : v) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -89,11 +81,12 @@ size_t ws_layout(const cmhd_ctx* c, size_t off[16]) {
   off[4] = o; o += align256(2 * plane * sizeof(double));         // ah
   off[5] = o; o += align256(FFT_PLANES * plane * sizeof(double2));  // fft
   off[6] = o; o += 256;                                          // reductions
-  off[7] = o; o += align256(zderiv_bytes(c->kp, c->grid.prec));  // z derivatives
+  off[7] = o;                                                    // (unused)
   off[8] = o; o += align256(2 * size_t(c->kp.nc_n) * sizeof(double));   // ln rho0, ln T0
   off[9] = o; o += align256(2 * plane * sizeof(double));         // driver snapshot 0
   off[10] = o; o += align256(2 * plane * sizeof(double));        // driver snapshot 1
   off[11] = o; o += align256(size_t(zt_size(c->kp)) * sizeof(double));  // z table
+  off[12] = o; o += align256(sizeof(KParams));                   // parameter block
   return o;
 }
 
@@ -175,6 +168,7 @@ void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
   p.kappa0 = q.kappa0;
   p.g_z = q.g_z;
   p.cv = q.R / (q.gamma - 1.0);
+  p.inv_cv = 1.0 / p.cv;
   p.gm1 = q.gamma - 1.0;
   for (int i = 0; i < 3; ++i) p.Bext[i] = q.Bext[i];
   p.B_floor2 = q.B_floor * q.B_floor;
@@ -271,6 +265,72 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
   return CMHD_OK;
 }
 
+// event pair for one timed launch of kernel `which` (or none when not profiling)
+hipError_t ev_begin(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev) {
+  ev = {nullptr, nullptr};
+  if (!c->profiling) return hipSuccess;
+  if (!c->ev_free.empty()) {
+    ev = c->ev_free.back();
+    c->ev_free.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e == hipSuccess) e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(ev.first, c->stream);
+}
+
+hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which) {
+  if (!c->profiling) return hipSuccess;
+  hipError_t e = hipEventRecord(ev.second, c->stream);
+  c->ev_pending[which].push_back(ev);
+  return e;
+}
+
+// the interior planes k0, k0+1 around height z and the weight a of k0+1
+// (non-uniform grids); false outside the interior
+bool plane_between(const cmhd_ctx* c, double z, int* k0, double* a) {
+  const int nz = c->kp.nz;
+  const double* zi = c->z_host.data() + NG;
+  if (!(z >= zi[0]) || !(z <= zi[nz - 1])) return false;
+  int k = int(std::upper_bound(zi, zi + nz, z) - zi) - 1;
+  k = std::min(k, nz - 2);
+  *k0 = k;
+  *a = (z - zi[k]) / (zi[k + 1] - zi[k]);
+  return true;
+}
+
+// the nudging target of a substage at time ts (snapshot pair: interpolated
+// into the u* buffer; single target: nothing to do)
+hipError_t driver_at(cmhd_ctx* c, double ts) {
+  if (!c->kp.solar || !c->snap) return hipSuccess;
+  const double w = std::min(1.0, std::max(0.0, (ts - c->snap_t0) / (c->snap_t1 - c->snap_t0)));
+  return launch_driver_interp(c->kp, c->u0, c->u1, w, c->uh, c->stream);
+}
+
+// One substage s from src to dst with the stage arguments a at the stage
+// time ts: the boundary work (ghost fill of src, the driver target at ts, the
+// nudged u_h ghost rows, which touch no plane of the fused kernel), then the
+// fused stencil/RHS/RK kernel.  Each part is timed when profiling is on.
+cmhd_status substage(cmhd_ctx* c, int s, double* src, double* dst, double* dF,
+                     const StageArgs& a, double ts) {
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  hipError_t e = ev_begin(c, ev);
+  if (e != hipSuccess) return hip_check(c, e, "profiling event");
+  cmhd_status st = do_fill(c, src);
+  if (st != CMHD_OK) return st;
+  e = driver_at(c, ts);
+  if (e == hipSuccess && c->kp.solar)
+    e = launch_ghost_rows(c->kp, src, dst, dF, c->uh, a, s > 0, s < 2, c->stream);
+  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_GHOSTS);
+  if (e == hipSuccess) e = ev_begin(c, ev);
+  if (e == hipSuccess)
+    e = launch_substage(c->kp, c->kp_dev, c->grid.prec, s, src, dst, dF, c->uh, c->ah, a,
+                        c->stream);
+  if (e == hipSuccess) e = ev_end(c, ev, CMHD_PROF_SUBSTAGE);
+  return hip_check(c, e, "substage launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -354,17 +414,6 @@ cmhd_status cmhd_init_grid_z(const cmhd_grid* grid, const cmhd_params* params, c
       c->nc_host[n + i] = lnT0_z ? lnT0_z[i] : 0.0;
     }
   }
-  {
-    hipError_t e = hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    c->ev_z.assign(size_t(plan_chunks(c->kp).nchunk), nullptr);
-    for (auto& ev : c->ev_z)
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      delete c;
-      return CMHD_EDEVICE;
-    }
-  }
   *out = c;
   return CMHD_OK;
 }
@@ -402,7 +451,6 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->ah = reinterpret_cast<double*>(c->ws + off[4]);
   c->fft = reinterpret_cast<double2*>(c->ws + off[5]);
   c->red = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
-  c->dz = c->ws + off[7];
   c->nc_dev = reinterpret_cast<double*>(c->ws + off[8]);
   c->u0 = reinterpret_cast<double*>(c->ws + off[9]);
   c->u1 = reinterpret_cast<double*>(c->ws + off[10]);
@@ -410,6 +458,7 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   c->zt_dev = reinterpret_cast<double*>(c->ws + off[11]);
   c->kp.ztab = c->zt_dev;
   c->kp.nc_tab = c->nc_dev;
+  c->kp_dev = reinterpret_cast<KParams*>(c->ws + off[12]);
   // driver targets start at zero; the stage buffers are fully written before use
   const size_t plane = size_t(c->grid.nx) * size_t(c->grid.ny);
   hipError_t e = hipMemsetAsync(c->uh, 0, 2 * plane * sizeof(double), c->stream);
@@ -420,6 +469,8 @@ cmhd_status cmhd_bind_workspace(cmhd_ctx* c, void* dev_ptr, size_t bytes) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->zt_dev, c->zt_host.data(), c->zt_host.size() * sizeof(double),
                        hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->kp_dev, &c->kp, sizeof(KParams), hipMemcpyHostToDevice, c->stream);
   // the tables are read from host vectors that outlive the copies
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return hip_check(c, e, "workspace clear");
@@ -497,101 +548,6 @@ cmhd_status cmhd_cfl_dt(cmhd_ctx* c, double* state, double* dt_out) {
   return do_cfl(c, state, dt_out);
 }
 
-// event pair for one timed launch of kernel `which` (or none when not profiling)
-hipError_t ev_begin(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev) {
-  ev = {nullptr, nullptr};
-  if (!c->profiling) return hipSuccess;
-  if (!c->ev_free.empty()) {
-    ev = c->ev_free.back();
-    c->ev_free.pop_back();
-  } else {
-    hipError_t e = hipEventCreate(&ev.first);
-    if (e == hipSuccess) e = hipEventCreate(&ev.second);
-    if (e != hipSuccess) return e;
-  }
-  return hipEventRecord(ev.first, c->stream);
-}
-
-hipError_t ev_end(cmhd_ctx* c, std::pair<hipEvent_t, hipEvent_t>& ev, int which) {
-  if (!c->profiling) return hipSuccess;
-  hipError_t e = hipEventRecord(ev.second, c->stream);
-  c->ev_pending[which].push_back(ev);
-  return e;
-}
-
-// the interior planes k0, k0+1 around height z and the weight a of k0+1
-// (non-uniform grids); false outside the interior
-bool plane_between(const cmhd_ctx* c, double z, int* k0, double* a) {
-  const int nz = c->kp.nz;
-  const double* zi = c->z_host.data() + NG;
-  if (!(z >= zi[0]) || !(z <= zi[nz - 1])) return false;
-  int k = int(std::upper_bound(zi, zi + nz, z) - zi) - 1;
-  k = std::min(k, nz - 2);
-  *k0 = k;
-  *a = (z - zi[k]) / (zi[k + 1] - zi[k]);
-  return true;
-}
-
-// the nudging target of a substage at time ts (snapshot pair: interpolated
-// into the u* buffer; single target: nothing to do)
-hipError_t driver_at(cmhd_ctx* c, double ts) {
-  if (!c->kp.solar || !c->snap) return hipSuccess;
-  const double w = std::min(1.0, std::max(0.0, (ts - c->snap_t0) / (c->snap_t1 - c->snap_t0)));
-  return launch_driver_interp(c->kp, c->u0, c->u1, w, c->uh, c->stream);
-}
-
-// one substage from src to dst (ghosts of src already filled): z-derivative
-// pass, fused stencil/RHS/RK kernel, nudged ghost rows.  On large grids the
-// substage is pipelined over z chunks: the z-derivative pass runs chunk by
-// chunk on the second stream (forked from the caller's stream) and the fused
-// kernel of chunk c waits only for the z derivatives of chunk c, so that the
-// streaming pass shares the CUs with the latency-bound fused kernel.  All work
-// is joined back into the caller's stream before the substage ends.
-hipError_t substage(cmhd_ctx* c, int s, const double* src, double* dst, double* dF,
-                    const StageArgs& a) {
-  const ChunkPlan cp = plan_chunks(c->kp);
-  const int prec = c->grid.prec;
-  std::pair<hipEvent_t, hipEvent_t> ev_all, ev_zd;
-  hipError_t e = ev_begin(c, ev_all);
-  if (!cp.pipelined) {
-    if (e == hipSuccess) e = ev_begin(c, ev_zd);
-    if (e == hipSuccess) e = launch_zderiv(c->kp, prec, src, c->dz, 0, c->kp.nz, c->stream);
-    if (e == hipSuccess) e = ev_end(c, ev_zd, CMHD_PROF_ZDERIV);
-    if (e == hipSuccess)
-      e = launch_rhs_rk(c->kp, prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, cp, 0, cp.nchunk,
-                        c->stream);
-  } else {
-    if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->zs, c->ev_fork, 0);
-    if (e == hipSuccess && c->profiling) {
-      // z-pass timing on its own stream
-      std::swap(c->stream, c->zs);
-      e = ev_begin(c, ev_zd);
-      std::swap(c->stream, c->zs);
-    }
-    for (int ch = 0; ch < cp.nchunk && e == hipSuccess; ++ch) {
-      const int k0 = ch * cp.kchunk, k1 = std::min(c->kp.nz, k0 + cp.kchunk);
-      e = launch_zderiv(c->kp, prec, src, c->dz, k0, k1, c->zs);
-      if (e == hipSuccess) e = hipEventRecord(c->ev_z[ch], c->zs);
-    }
-    if (e == hipSuccess && c->profiling) {
-      std::swap(c->stream, c->zs);
-      e = ev_end(c, ev_zd, CMHD_PROF_ZDERIV);
-      std::swap(c->stream, c->zs);
-    }
-    for (int ch = 0; ch < cp.nchunk && e == hipSuccess; ++ch) {
-      e = hipStreamWaitEvent(c->stream, c->ev_z[ch], 0);
-      if (e == hipSuccess)
-        e = launch_rhs_rk(c->kp, prec, s, src, c->dz, dst, dF, c->uh, c->ah, a, cp, ch, 1,
-                          c->stream);
-    }
-  }
-  if (e == hipSuccess) e = ev_end(c, ev_all, CMHD_PROF_SUBSTAGE);
-  if (e == hipSuccess && c->kp.solar)
-    e = launch_ghost_rows(c->kp, src, dst, dF, c->uh, a, s > 0, s < 2, c->stream);
-  return e;
-}
-
 cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, double* dt_used) {
   if (!c || !state || !t) return CMHD_EINVAL;
   cmhd_status st = need_ws(c);
@@ -603,12 +559,10 @@ cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, doub
   double* src[3] = {state, c->W1, c->W2};
   double* dst[3] = {c->W1, c->W2, state};
   for (int s = 0; s < 3; ++s) {
-    st = do_fill(c, src[s]);
+    const double ts = *t + RK_C[s] * dt;
+    StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, ts)};
+    st = substage(c, s, src[s], dst[s], c->dF, a, ts);
     if (st != CMHD_OK) return st;
-    StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, *t + RK_C[s] * dt)};
-    hipError_t e = driver_at(c, *t + RK_C[s] * dt);
-    if (e == hipSuccess) e = substage(c, s, src[s], dst[s], c->dF, a);
-    if (e != hipSuccess) return hip_check(c, e, "rk3 substage launch");
   }
   *t += dt;
   if (dt_used) *dt_used = dt;
@@ -619,13 +573,9 @@ cmhd_status cmhd_eval_rhs(cmhd_ctx* c, double* state, double t, double* rhs) {
   if (!c || !state || !rhs) return CMHD_EINVAL;
   cmhd_status st = need_ws(c);
   if (st != CMHD_OK) return st;
-  st = do_fill(c, state);
-  if (st != CMHD_OK) return st;
   // one substage with alpha = 0, beta = 0, dt = 1: dF = RHS, f_next = f (into W1)
   StageArgs a{0.0, 0.0, 1.0, ramp(c, t)};
-  hipError_t e = driver_at(c, t);
-  if (e == hipSuccess) e = substage(c, 0, state, c->W1, rhs, a);
-  return hip_check(c, e, "eval_rhs launch");
+  return substage(c, 0, state, c->W1, rhs, a, t);
 }
 
 cmhd_status cmhd_get_fields(cmhd_ctx* c, const double* state, unsigned mask, double* dst,
@@ -725,12 +675,9 @@ cmhd_status need_adj(cmhd_ctx* c) {
 
 // forward substage s from src to dst (fills the ghosts of src first)
 cmhd_status fwd_stage(cmhd_ctx* c, int s, double* src, double* dst, double t, double dt) {
-  cmhd_status st = do_fill(c, src);
-  if (st != CMHD_OK) return st;
-  StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, t + RK_C[s] * dt)};
-  hipError_t e = driver_at(c, t + RK_C[s] * dt);
-  if (e == hipSuccess) e = substage(c, s, src, dst, c->dF, a);
-  return hip_check(c, e, "forward substage");
+  const double ts = t + RK_C[s] * dt;
+  StageArgs a{RK_ALPHA[s], RK_BETA[s], dt, ramp(c, ts)};
+  return substage(c, s, src, dst, c->dF, a, ts);
 }
 
 }  // namespace
@@ -861,7 +808,7 @@ cmhd_status cmhd_profile_enable(cmhd_ctx* c, int enable) {
 
 cmhd_status cmhd_profile_read(cmhd_ctx* c, int which, double* ms, int* launches) {
   if (!c || !ms || !launches) return CMHD_EINVAL;
-  if (which != CMHD_PROF_SUBSTAGE && which != CMHD_PROF_ZDERIV)
+  if (which != CMHD_PROF_SUBSTAGE && which != CMHD_PROF_GHOSTS)
     return fail(c, CMHD_EINVAL, "unknown kernel selector");
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_check(c, e, "profile sync");

@@ -30,7 +30,7 @@ struct KParams {
   double dx, dy, dz, z0;
   double i60dx, i60dy, i60dz;      // 1/(60 h)
   double i180dx2, i180dy2, i180dz2;  // 1/(180 h^2)
-  double gamma, R, mu0, inv_mu0, eta, nu, D_rho, kappa0, g_z, cv, gm1;
+  double gamma, R, mu0, inv_mu0, eta, nu, D_rho, kappa0, g_z, cv, inv_cv, gm1;
   double Bext[3];
   double B_floor2;
   double eta_s, chi_s, chi_rho, z_s, z_t;

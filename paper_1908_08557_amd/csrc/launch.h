@@ -7,25 +7,17 @@
 
 namespace cmhd {
 
-// bytes of the z-derivative buffer (16 slots of nz planes, in the precision
-// of the right-hand side)
-size_t zderiv_bytes(const KParams& p, int prec);
-// How a substage is cut into z chunks: the fused kernel marches kchunk planes
-// per block.  pipelined: one fused launch per chunk, the z-derivative pass of
-// chunk c overlapping the fused kernel of chunk c-1 on a second stream.
-struct ChunkPlan {
+// How a substage is cut into z chunks: each block of the fused substage
+// kernel marches kchunk planes of one 16 x 16 tile.
+struct SubstagePlan {
   int kchunk, nchunk;
-  bool pipelined;
 };
-ChunkPlan plan_chunks(const KParams& p);
-// z derivatives of planes [k0, k1)
-hipError_t launch_zderiv(const KParams& p, int prec, const double* f, void* dz, int k0, int k1,
-                         hipStream_t s);
-// fused substage kernel over the chunks [chunk0, chunk0 + nchunks) of the plan
-hipError_t launch_rhs_rk(const KParams& p, int prec, int stage, const double* f, const void* dz,
-                         double* fo, double* dF, const double* uh, const double* ah,
-                         StageArgs st, const ChunkPlan& cp, int chunk0, int nchunks,
-                         hipStream_t s);
+SubstagePlan plan_substage(const KParams& p);
+// one substage from f to fo: stencils, right-hand side and 2N-RK3 update of
+// every interior zone (ghosts of f filled); pg: a device copy of p
+hipError_t launch_substage(const KParams& p, const KParams* pg, int prec, int stage,
+                           const double* f, double* fo, double* dF, const double* uh,
+                           const double* ah, StageArgs st, hipStream_t s);
 hipError_t launch_ghost_rows(const KParams& p, const double* f, double* fo, double* dF,
                              const double* uh, StageArgs st, int read_dF, int write_dF,
                              hipStream_t s);

@@ -26,13 +26,16 @@
 //
 // Source interface (f a field index, slot a Hessian slot xx yy zz xy xz yz):
 //   S v(f); double v64(f); S d(f, dir); S h(f, slot); S lapr();
+//   void gh(f, S g[3], S h[6]): gradient and Hessian of f together (only the
+//   Hessian slots the equations use need be filled);
 //   kUnrollA, kUnrollU: unroll factors of the component loops over A and u
 //   (1 keeps a source's on-demand reads in a rolled loop).
-// h(f, slot) is only asked for the slots the equations use.
 //
-// The evaluation is split into a magnetic part (the only one that reads A's
-// derivatives) and a fluid part, so that a kernel can release its staged
-// copy of A between the two; rhs_eval runs both.
+// The evaluation is split into pieces that a kernel may run on different
+// waves: the magnetic part (induction, B, J, the Spitzer field direction),
+// the terms it hands to the fluid equations (Lorentz force, Ohmic and
+// conductive heating, the swamp diffusion of ln T), the rest of the fluid
+// equations, and the boundary terms; rhs_eval runs them all.
 #pragma once
 
 #include <type_traits>
@@ -108,7 +111,7 @@ __device__ __forceinline__ int rad_segment(const Tab& t, int n, double x) {
 
 #define CMHD_FENCE() __builtin_amdgcn_sched_barrier(0)
 
-// what the fluid part needs of the magnetic part
+// what the fluid equations need of the magnetic part
 template <typename S>
 struct MagState {
   S b[3], iBn;     // field direction and 1/|B|_r (Spitzer)
@@ -116,36 +119,32 @@ struct MagState {
   S JxB[3], ohm;   // Lorentz force, eta mu0 J^2 / mu0
 };
 
+// Induction equation (out[AX..AZ]) and the magnetic quantities of the fluid
+// equations.  Each component of A is read as its gradient and Hessian at
+// once (src.gh), and B = curl A + B_ext, div A, d_j B_i and lap A are
+// accumulated component by component:
+//   B_x = d_y A_z - d_z A_y,  B_y = d_z A_x - d_x A_z,  B_z = d_x A_y - d_y A_x
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& pc,
                                              const KParams& p, S out[NF], MagState<S>& m) {
   const S w = S(pc.w), dw = S(pc.dw);
-  const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
-
-  // ================= magnetic phase: B, grad B, induction ===================
-  S B[3], divA;
-  {
-    const S Axy = src.d(AX, 1), Axz = src.d(AX, 2), Ayx = src.d(AY, 0);
-    const S Ayz = src.d(AY, 2), Azx = src.d(AZ, 0), Azy = src.d(AZ, 1);
-    B[0] = Azy - Ayz + S(p.Bext[0]);
-    B[1] = Axz - Azx + S(p.Bext[1]);
-    B[2] = Ayx - Axy + S(p.Bext[2]);
-    divA = src.d(AX, 0) + src.d(AY, 1) + src.d(AZ, 2);
-  }
-  // dB[i][j] = d_j B_i from the second derivatives of A (each mixed one read once):
-  //   B_x = d_y A_z - d_z A_y,  B_y = d_z A_x - d_x A_z,  B_z = d_x A_y - d_y A_x
+  S B[3] = {S(0.0), S(0.0), S(0.0)}, divA = S(0.0);
   S dB[3][3], lapA[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i) {
+    lapA[i] = S(0.0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) dB[i][j] = S(0.0);
-  // a rolled loop over the components when the source allows it: each
-  // component's stencil reads then form their own scheduling region
+  }
 #pragma unroll(Src::kUnrollA)
   for (int c = 0; c < 3; ++c) {
-    S h[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) h[s] = src.h(AX + c, s);
+    S g[3], h[6];
+    src.gh(AX + c, g, h);
+    const S gc = c == 0 ? g[0] : (c == 1 ? g[1] : g[2]);
+    divA = divA + gc;
+    B[0] = B[0] + (c == AZ ? g[1] : (c == AY ? -g[2] : S(0.0)));
+    B[1] = B[1] + (c == AX ? g[2] : (c == AZ ? -g[0] : S(0.0)));
+    B[2] = B[2] + (c == AY ? g[0] : (c == AX ? -g[1] : S(0.0)));
     const S lap = h[0] + h[1] + h[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) lapA[i] = (i == c) ? lap : lapA[i];
@@ -157,8 +156,11 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
       dB[2][j] = dB[2][j] + (c == AX ? -hj1 : (c == AY ? hj0 : S(0.0)));
     }
   }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) B[i] = B[i] + S(p.Bext[i]);
   const S cB[3] = {dB[2][1] - dB[1][2], dB[0][2] - dB[2][0], dB[1][0] - dB[0][1]};  // mu0 J
   {
+    const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
     const S uxB[3] = {uy * B[2] - uz * B[1], uz * B[0] - ux * B[2], ux * B[1] - uy * B[0]};
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -192,6 +194,76 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   m.ohm = ohm;
 }
 
+// rho and T (float path: from the float64 state, since ln rho ~ 20 and
+// ln T ~ 14 carry too few bits in float)
+template <typename S, class Src>
+__device__ __forceinline__ void rho_T(const Src& src, S& rho, S& T) {
+  if constexpr (std::is_same<S, float>::value) {
+    rho = float(exp(src.v64(LR)));
+    T = float(exp(src.v64(LT)));
+  } else {
+    rho = s_exp(src.v(LR));
+    T = s_exp(src.v(LT));
+  }
+}
+
+// The terms of the fluid equations that need the magnetic part or the
+// Hessian of ln T, in two pieces: rhs_lorentz gives J x B / rho (momentum),
+// rhs_heating (eta mu0 J^2 / mu0) / (rho c_v T) + Q_cond / (rho c_v T)
+// + chi_s w lap ln T (energy in ln T, Sect. 3 and eq. 19).  Spitzer, with G,
+// H the gradient and Hessian of ln T and b = B/|B|_r:
+//   Q_cond / (rho c_v T) = (kappa0 T^5/2 / (rho c_v))
+//       [7/2 (b.G)^2 + b b:H + (b_i d_i B_j G_j - 2 (b.G) b_i b_k d_i B_k) / |B|_r]
+// (the float path forms the coefficient kappa0 T^5/2 / (rho c_v) in float64).
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_lorentz(const Src& src, const MagState<S>& m, S add[3]) {
+  S rho, T;
+  rho_T(src, rho, T);
+  const S irho = S(1.0) / rho;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) add[i] = m.JxB[i] * irho;
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ S rhs_heating(const Src& src, const PointCtx<S>& pc,
+                                         const KParams& p, const MagState<S>& m) {
+  constexpr bool kFloat = std::is_same<S, float>::value;
+  S rho, T;
+  rho_T(src, rho, T);
+  S e = m.ohm / (rho * S(p.cv) * T);
+  const bool swamp_T = p.chi_s != 0.0 && pc.w != 0.0;
+  if (p.kappa0 != 0.0 || swamp_T) {
+    S G[3], H[6];
+    src.gh(LT, G, H);
+    if (p.kappa0 != 0.0) {
+      const S* b = m.b;
+      const S* vv = m.vv;
+      const S bG = b[0] * G[0] + b[1] * G[1] + b[2] * G[2];
+      const S bbH = b[0] * b[0] * H[0] + b[1] * b[1] * H[1] + b[2] * b[2] * H[2] +
+                    S(2.0) * (b[0] * b[1] * H[3] + b[0] * b[2] * H[4] + b[1] * b[2] * H[5]);
+      const S vG = vv[0] * G[0] + vv[1] * G[1] + vv[2] * G[2];
+      const S bracket = S(3.5) * bG * bG + bbH + (vG - S(2.0) * bG * m.sbb) * m.iBn;
+      S kc;
+      if constexpr (kFloat) {
+        kc = float(p.kappa0 * exp(2.5 * src.v64(LT) - src.v64(LR)) * p.inv_cv);   // FP64 coefficient
+      } else {
+        kc = S(p.kappa0) * s_exp(S(2.5) * src.v(LT) - src.v(LR)) * S(p.inv_cv);
+      }
+      e = e + kc * bracket;
+    }
+    if (swamp_T) e = e + S(p.chi_s) * S(pc.w) * (H[0] + H[1] + H[2]);
+  }
+  return e;
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_mag_to_fluid(const Src& src, const PointCtx<S>& pc,
+                                                 const KParams& p, const MagState<S>& m,
+                                                 S add[4]) {
+  rhs_lorentz<S>(src, m, add);
+  add[3] = rhs_heating<S>(src, pc, p, m);
+}
+
 // optically thin loss Q_rad/(rho c_v T) = exp(ln rho + lnL(ln T) - ln T) W(ln T) / c_v
 // (the only table lookup of the right-hand side)
 template <typename S, class Src, class Tab>
@@ -223,7 +295,7 @@ __device__ __forceinline__ S rhs_radiation(const Src& src, const KParams& p, con
                               : S(tab.lnL(i)) + S(tab.slope(i)) * (src.v(LT) - S(tab.lnT(i)));
         ex = src.v(LR) + lnL - src.v(LT);
       }
-      rad = s_exp(ex) * wc * S(1.0 / p.cv);
+      rad = s_exp(ex) * wc * S(p.inv_cv);
     }
   }
   return rad;
@@ -277,139 +349,152 @@ __device__ __forceinline__ S rhs_newton(const Src& src, const KParams& p, const 
   else return term;
 }
 
+// Momentum without the Lorentz force:
+//   du/dt = -(u.grad)u - R T grad(ln rho + ln T) + g e_z
+//           + nu (lap u + grad div u / 3 + 2 S.grad ln rho)
+// and the two scalars of the velocity gradient the other equations need,
+// div u and S:S (S the traceless rate of strain).  The gradient a_ij = d_j u_i
+// is streamed component by component (few values alive): with G = grad ln rho,
+//   2 (S.G)_i = sum_j a_ij G_j + sum_j a_ji G_j - 2/3 div u G_i,
+//   S:S = 1/2 sum_ij a_ij^2 + 1/2 sum_ij a_ij a_ji - (div u)^2 / 3,
+// and grad div u takes the c-th Hessian column of u_c.
 template <typename S, class Src>
-__device__ __forceinline__ void rhs_fluid(const Src& src, const PointCtx<S>& pc,
-                                          const KParams& p, const MagState<S>& m, S rad,
-                                          S nc, S out[NF]) {
-  constexpr bool kFloat = std::is_same<S, float>::value;
-  const S w = S(pc.w);
-  const S ux = src.v(UX), uy = src.v(UY), uz = src.v(UZ);
-  const S* JxB = m.JxB;
-  const S* b = m.b;
-  const S* vv = m.vv;
-  const S iBn = m.iBn, sbb = m.sbb, ohm = m.ohm;
-
-  // ================= momentum ===============================================
-  S rho, T;
-  if constexpr (kFloat) {
-    rho = float(exp(src.v64(LR)));   // ln rho ~ 20 and ln T ~ 14 carry too few bits in float
-    T = float(exp(src.v64(LT)));
-  } else {
-    rho = s_exp(src.v(LR));
-    T = s_exp(src.v(LT));
-  }
-  const S irho = S(1.0) / rho;
+__device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S out[NF],
+                                             S& divu_out, S& SS_out) {
+  const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   const S Glr[3] = {src.d(LR, 0), src.d(LR, 1), src.d(LR, 2)};
-  const S GlT[3] = {src.d(LT, 0), src.d(LT, 1), src.d(LT, 2)};
-  S divu, SS;
+  S mom[3], divu = S(0.0), sq = S(0.0), cross = S(0.0);
+  S a01 = S(0.0), a02 = S(0.0), a12 = S(0.0);   // a_01, a_02, a_12 for the cross sum
   {
-    S Gu[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) Gu[c][d] = src.d(UX + c, d);
-    divu = Gu[0][0] + Gu[1][1] + Gu[2][2];
-    S Sij[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) Sij[i][j] = S(0.5) * (Gu[i][j] + Gu[j][i]);
-    const S third_div = divu * S(1.0 / 3.0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Sij[i][i] = Sij[i][i] - third_div;
-    SS = S(0.0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) SS = SS + Sij[i][j] * Sij[i][j];
-    // Laplacian of u_c and grad div u (mixed slots: xy, xz for u_x; xy, yz
-    // for u_y; xz, yz for u_z)
-    S lapu[3], gd[3] = {S(0.0), S(0.0), S(0.0)};
-#pragma unroll(Src::kUnrollU)
-    for (int c = 0; c < 3; ++c) {
-      const S hxx = src.h(UX + c, 0), hyy = src.h(UX + c, 1), hzz = src.h(UX + c, 2);
-      const S lap = hxx + hyy + hzz;
-      // mixed slots of grad div u: xy for u_x, u_y; xz for u_x, u_z; yz for u_y, u_z
-      const S m1 = src.h(UX + c, c == 0 ? 3 : (c == 1 ? 3 : 4));   // xy, xy, xz
-      const S m2 = src.h(UX + c, c == 0 ? 4 : 5);                  // xz, yz, yz
-#pragma unroll
-      for (int i = 0; i < 3; ++i) lapu[i] = (i == c) ? lap : lapu[i];
-      // gd_i += d_i d_c u_c
-      gd[0] = gd[0] + (c == 0 ? hxx : m1);
-      gd[1] = gd[1] + (c == 0 ? m1 : (c == 1 ? hyy : m2));
-      gd[2] = gd[2] + (c == 2 ? hzz : m2);
-    }
+    S T;
+    if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
+    else T = s_exp(src.v(LT));
     const S RT = S(p.R) * T;
-    const S u[3] = {ux, uy, uz};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const S adv = u[0] * Gu[i][0] + u[1] * Gu[i][1] + u[2] * Gu[i][2];
-      const S press = -RT * (Glr[i] + GlT[i]);
-      const S strain = Sij[i][0] * Glr[0] + Sij[i][1] * Glr[1] + Sij[i][2] * Glr[2];
-      const S visc = S(p.nu) * (lapu[i] + gd[i] * S(1.0 / 3.0) + S(2.0) * strain);
-      out[UX + i] = press - adv + JxB[i] * irho + visc;
-    }
-    out[UZ] = out[UZ] + S(p.g_z);
+    for (int i = 0; i < 3; ++i) mom[i] = -RT * (Glr[i] + src.d(LT, i));
   }
-  CMHD_FENCE();
+#pragma unroll(Src::kUnrollU)
+  for (int c = 0; c < 3; ++c) {
+    S g[3], h[6];
+    src.gh(UX + c, g, h);   // g[j] = a_cj
+    // advection, the Laplacian of u_c and sum_j a_cj G_j (into mom[c], with
+    // selects so that a rolled loop indexes no register array)
+    const S own = -(u[0] * g[0] + u[1] * g[1] + u[2] * g[2]) +
+                  S(p.nu) * (h[0] + h[1] + h[2] + g[0] * Glr[0] + g[1] * Glr[1] + g[2] * Glr[2]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mom[i] = mom[i] + (i == c ? own : S(0.0));
+    // grad div u: d_i d_c u_c (Hessian column c), and a_ci G_c into component i
+    const S Gc = c == 0 ? Glr[0] : (c == 1 ? Glr[1] : Glr[2]);
+    const S hc[3] = {c == 0 ? h[0] : (c == 1 ? h[3] : h[4]),
+                     c == 0 ? h[3] : (c == 1 ? h[1] : h[5]),
+                     c == 0 ? h[4] : (c == 1 ? h[5] : h[2])};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      mom[i] = mom[i] + S(p.nu) * (hc[i] * S(1.0 / 3.0) + g[i] * Gc);
+    divu = divu + (c == 0 ? g[0] : (c == 1 ? g[1] : g[2]));
+    sq = sq + (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    // a_ij a_ji: the diagonal now, the off-diagonal pairs as their second member arrives
+    if (c == 0) {
+      cross = cross + g[0] * g[0];
+      a01 = g[1];
+      a02 = g[2];
+    } else if (c == 1) {
+      cross = cross + g[1] * g[1] + S(2.0) * g[0] * a01;
+      a12 = g[2];
+    } else {
+      cross = cross + g[2] * g[2] + S(2.0) * (g[0] * a02 + g[1] * a12);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    out[UX + i] = mom[i] - S(p.nu) * S(2.0 / 3.0) * divu * Glr[i];
+  out[UZ] = out[UZ] + S(p.g_z);
+  divu_out = divu;
+  SS_out = S(0.5) * (sq + cross) - divu * divu * S(1.0 / 3.0);
+}
 
-  // ================= continuity in ln rho (Sect. 2.5, eq. 20) ================
+// Continuity in ln rho (Sect. 2.5, eq. 20) and energy in ln T without the
+// Ohmic, conductive and swamp terms (those come from rhs_mag_to_fluid):
+//   dlnrho = -u.grad ln rho - div u + (D_rho + chi_rho w) lap ln rho + D_rho |grad ln rho|^2
+//   dlnT   = -u.grad ln T - (gamma-1) div u + 2 rho nu S:S / (rho c_v T) - Q_rad/(rho c_v T)
+//            (+ Newtonian cooling)
+// with div u and S:S from rhs_momentum.
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_scalars(const Src& src, const PointCtx<S>& pc,
+                                            const KParams& p, S divu, S SS, S rad, S nc,
+                                            S out[NF]) {
+  const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   {
-    const S udr = ux * Glr[0] + uy * Glr[1] + uz * Glr[2];
+    const S Glr[3] = {src.d(LR, 0), src.d(LR, 1), src.d(LR, 2)};
+    const S udr = u[0] * Glr[0] + u[1] * Glr[1] + u[2] * Glr[2];
     const S gr2 = Glr[0] * Glr[0] + Glr[1] * Glr[1] + Glr[2] * Glr[2];
-    out[LR] = (S(p.D_rho) + S(p.chi_rho) * w) * src.lapr() - udr - divu + S(p.D_rho) * gr2;
+    out[LR] = (S(p.D_rho) + S(p.chi_rho) * S(pc.w)) * src.lapr() - udr - divu + S(p.D_rho) * gr2;
   }
-
-  // ================= energy in ln T ===========================================
-  const S vheat = S(2.0) * rho * S(p.nu) * SS;
-  const S heat = (ohm + vheat) * irho / (S(p.cv) * T);
-  S lapT, cond = S(0.0);
   {
-    const S hxx = src.h(LT, 0), hyy = src.h(LT, 1), hzz = src.h(LT, 2);
-    lapT = hxx + hyy + hzz;
-    if (p.kappa0 != 0.0) {
-      const S hxy = src.h(LT, 3), hxz = src.h(LT, 4), hyz = src.h(LT, 5);
-      const S bG = b[0] * GlT[0] + b[1] * GlT[1] + b[2] * GlT[2];
-      const S bbH = b[0] * b[0] * hxx + b[1] * b[1] * hyy + b[2] * b[2] * hzz +
-                    S(2.0) * (b[0] * b[1] * hxy + b[0] * b[2] * hxz + b[1] * b[2] * hyz);
-      const S vG = vv[0] * GlT[0] + vv[1] * GlT[1] + vv[2] * GlT[2];
-      const S bracket = S(3.5) * bG * bG + bbH + (vG - S(2.0) * bG * sbb) * iBn;
-      S kc;
-      if constexpr (kFloat) {
-        kc = float(p.kappa0 * exp(2.5 * src.v64(LT) - src.v64(LR)) / p.cv);   // FP64 coefficient
-      } else {
-        kc = S(p.kappa0) * s_exp(S(2.5) * src.v(LT) - src.v(LR)) * S(1.0 / p.cv);
-      }
-      cond = kc * bracket;
-    }
+    S T;
+    if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
+    else T = s_exp(src.v(LT));
+    const S udT = u[0] * src.d(LT, 0) + u[1] * src.d(LT, 1) + u[2] * src.d(LT, 2);
+    out[LT] = S(2.0) * S(p.nu) * SS / (S(p.cv) * T) - rad - udT - S(p.gm1) * divu + nc;
   }
+}
 
-  {
-    const S udT = ux * GlT[0] + uy * GlT[1] + uz * GlT[2];
-    out[LT] = heat + cond - rad - udT - S(p.gm1) * divu + S(p.chi_s) * w * lapT + nc;
-  }
+// the fluid equations without the magnetic terms: momentum, continuity, energy
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_fluid_core(const Src& src, const PointCtx<S>& pc,
+                                               const KParams& p, S rad, S nc, S out[NF]) {
+  S divu, SS;
+  rhs_momentum<S>(src, p, out, divu, SS);
+  rhs_scalars<S>(src, pc, p, divu, SS, rad, nc, out);
+}
 
-  // ================= photospheric nudging and boundary points ================
+// the magnetic part's contributions added to the fluid equations
+template <typename S>
+__device__ __forceinline__ void rhs_add_magnetic(const S add[4], S out[NF]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[UX + i] = out[UX + i] + add[i];
+  out[LT] = out[LT] + add[3];
+}
+
+// photospheric nudging of A_h toward A_h* (magnetic equations)
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_boundary_magnetic(const Src& src, const PointCtx<S>& pc,
+                                                      const KParams& p, S out[NF]) {
   if (pc.bottom) {
-    out[UX] = out[UX] - S(p.tau_u) * (ux - S(pc.ramp) * pc.uh[0]);
-    out[UY] = out[UY] - S(p.tau_u) * (uy - S(pc.ramp) * pc.uh[1]);
     out[AX] = out[AX] - S(p.tau_A) * (src.v(AX) - pc.ah[0]);
     out[AY] = out[AY] - S(p.tau_A) * (src.v(AY) - pc.ah[1]);
+  }
+}
+
+// photospheric nudging of u_h toward s(t) u* (eq. 5) and the boundary
+// points: u_z = 0 at both boundary planes, ln rho fixed at the photosphere
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_boundary_fluid(const Src& src, const PointCtx<S>& pc,
+                                                   const KParams& p, S out[NF]) {
+  if (pc.bottom) {
+    out[UX] = out[UX] - S(p.tau_u) * (src.v(UX) - S(pc.ramp) * pc.uh[0]);
+    out[UY] = out[UY] - S(p.tau_u) * (src.v(UY) - S(pc.ramp) * pc.uh[1]);
     out[UZ] = S(0.0);
     out[LR] = S(0.0);
   }
   if (pc.top) out[UZ] = S(0.0);
 }
 
+// the whole right-hand side at one zone
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
                                          const KParams& p, S out[NF]) {
   MagState<S> m;
+  S add[4];
   const S rad = rhs_radiation<S>(src, p, ParamRadTable{p});
   const S nc = rhs_newton<S>(src, p, ParamNcTable{p}, pc);
   rhs_magnetic<S>(src, pc, p, out, m);
+  rhs_mag_to_fluid<S>(src, pc, p, m, add);
   CMHD_FENCE();
-  rhs_fluid<S>(src, pc, p, m, rad, nc, out);
+  rhs_fluid_core<S>(src, pc, p, rad, nc, out);
+  rhs_add_magnetic<S>(add, out);
+  rhs_boundary_magnetic<S>(src, pc, p, out);
+  rhs_boundary_fluid<S>(src, pc, p, out);
 }
 
 }  // namespace cmhd

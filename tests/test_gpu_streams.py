@@ -51,14 +51,14 @@ def test_profile_counts_and_resets():
     dt = s.cfl_dt(x)
     s.profile(True)
     s.profile_read("substage")
-    s.profile_read("zderiv")
+    s.profile_read("ghosts")
     t = 0.0
     for _ in range(2):
         t, _ = s.rk3_step(x, t, dt)
     ms, n = s.profile_read("substage")
-    zms, zn = s.profile_read("zderiv")
+    gms, gn = s.profile_read("ghosts")
     assert n == 6 and ms > 0.0          # three substages per step
-    assert zn == 6 and zms > 0.0        # one z pass per substage (not pipelined here)
+    assert gn == 6 and gms > 0.0        # the boundary work of every substage
     assert s.profile_read("substage") == (0.0, 0)
     s.profile(False)
     s.rk3_step(x, t, dt)
