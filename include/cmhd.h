@@ -229,6 +229,20 @@ cmhd_status cmhd_eval_rhs(cmhd_ctx* ctx, double* state, double t, double* rhs);
  * limits over the interior (fills the ghosts first).  Synchronous. */
 cmhd_status cmhd_cfl_dt(cmhd_ctx* ctx, double* state, double* dt_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight stepping loops, harnesses that forbid allocation): the time
+ * step of cmhd_cfl_dt for a state whose ghost planes are already filled
+ * (cmhd_fill_ghosts; this call does not fill them), with the reduction
+ * scratch in a fixed array inside the library (256 bytes per GPU, kept until
+ * the process ends) instead of the bound workspace.  It allocates nothing and
+ * needs no workspace, except on a non-uniform z grid (whose z table lives in
+ * the workspace: CMHD_ESTATE without one).  Any grid the context accepts is
+ * accepted (the scratch holds three maxima whatever the size).  The
+ * context's GPU must be current (CMHD_ESTATE otherwise).  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and may return a wrong dt.  Synchronous. */
+cmhd_status cmhd_cfl_dt_noalloc(cmhd_ctx* ctx, const double* state, double* dt_out);
+
 /* Copy the fields selected by mask (bit f = field f) to dst, packed in field
  * order as [nsel][nz][ny][nx] (with_ghosts = 0) or [nsel][nz+6][ny][nx].
  * dst_on_host != 0: dst is host memory and the call is synchronous. */

@@ -84,6 +84,7 @@ def load():
         "cmhd_fill_ghosts": (I, [P, P, D]),
         "cmhd_rk3_step": (I, [P, P, ctypes.POINTER(D), D, ctypes.POINTER(D)]),
         "cmhd_cfl_dt": (I, [P, P, ctypes.POINTER(D)]),
+        "cmhd_cfl_dt_noalloc": (I, [P, P, ctypes.POINTER(D)]),
         "cmhd_eval_rhs": (I, [P, P, D, P]),
         "cmhd_get_fields": (I, [P, P, U, P, I, I]),
         "cmhd_set_fields": (I, [P, P, U, P, I, I]),
@@ -121,7 +122,7 @@ def exported_symbols():
     return ["cmhd_init_grid", "cmhd_init_grid_z", "cmhd_state_elems", "cmhd_workspace_bytes", "cmhd_bind_workspace",
             "cmhd_set_stream", "cmhd_set_driver", "cmhd_set_driver_snapshots",
             "cmhd_fill_ghosts", "cmhd_rk3_step",
-            "cmhd_cfl_dt", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_set_fields", "cmhd_bz_plane", "cmhd_check_finite",
+            "cmhd_cfl_dt", "cmhd_cfl_dt_noalloc", "cmhd_eval_rhs", "cmhd_get_fields", "cmhd_set_fields", "cmhd_bz_plane", "cmhd_check_finite",
             "cmhd_adjoint_workspace_bytes", "cmhd_bind_adjoint_workspace", "cmhd_rk3_step_jvp",
             "cmhd_rk3_step_vjp", "cmhd_bz_plane_vjp",
             "cmhd_profile_enable", "cmhd_profile_read", "cmhd_last_error", "cmhd_destroy",
@@ -271,6 +272,14 @@ class Solver:
         self._stream()
         dt = ctypes.c_double(0.0)
         self._check(self.lib.cmhd_cfl_dt(self.ctx, self._state(state), ctypes.byref(dt)))
+        return dt.value
+
+    def cfl_dt_noalloc(self, state):
+        """cmhd_cfl_dt_noalloc: the time step of a state whose ghost planes are
+        filled, with the library's fixed device scratch (allocates nothing)."""
+        self._stream()
+        dt = ctypes.c_double(0.0)
+        self._check(self.lib.cmhd_cfl_dt_noalloc(self.ctx, self._state(state), ctypes.byref(dt)))
         return dt.value
 
     def get_fields(self, state, mask=0xFF, with_ghosts=False):

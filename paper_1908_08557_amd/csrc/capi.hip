@@ -6,16 +6,42 @@
 #include <string>
 #include <utility>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "launch.h"
 
 using namespace cmhd;
 
+// Reduction scratch of cmhd_cfl_dt_noalloc: the three maxima of the CFL
+// kernel (3 x 8 bytes, padded), one copy per GPU held until the process ends.
+// In host code this name is a stand-in, not a device address: the address of
+// each GPU's copy is looked up once per device (init_noalloc_scratch) and only
+// that pointer is handed to kernels.
+static __device__ __align__(256) unsigned long long scratch[32];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned long long* g_scratch[kMaxDevices] = {};   // per device: &scratch on that GPU
+
+// look up this device's copy of the scratch array (the device is current)
+hipError_t init_noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[dev] = static_cast<unsigned long long*>(ptr);
+  return e;
+}
+}  // namespace
+
 struct cmhd_ctx {
   cmhd_grid grid;
   cmhd_params par;
   KParams kp;
+  int dev = 0;            // the GPU current at init
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -231,15 +257,9 @@ cmhd_status do_fill(cmhd_ctx* c, double* state) {
   return hip_check(c, e, "fill_ghosts launch");
 }
 
-cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
-  cmhd_status st = do_fill(c, state);
-  if (st != CMHD_OK) return st;
-  hipError_t e = launch_cfl_max(c->kp, state, c->red, c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "cfl launch");
-  unsigned long long h[3];
-  e = hipMemcpyAsync(h, c->red, sizeof(h), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "cfl copy");
+// dt from the three maxima of the CFL kernel (speed / spacing or speed,
+// diffusivity / spacing^2 or diffusivity, radiative rate) and the nudging rates
+cmhd_status dt_from_maxima(cmhd_ctx* c, const unsigned long long h[3], double* dt_out) {
   double m[3];
   std::memcpy(m, h, sizeof(m));
   const KParams& p = c->kp;
@@ -263,6 +283,25 @@ cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
     return fail(c, CMHD_EDT, "the time step from the CFL limits is " + std::to_string(dt));
   *dt_out = dt;
   return CMHD_OK;
+}
+
+// the CFL maxima of a ghost-filled state reduced into red (3 values), copied
+// to the host and turned into dt
+cmhd_status cfl_reduce(cmhd_ctx* c, const double* state, unsigned long long* red,
+                       double* dt_out) {
+  hipError_t e = launch_cfl_max(c->kp, state, red, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "cfl launch");
+  unsigned long long h[3];
+  e = hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "cfl copy");
+  return dt_from_maxima(c, h, dt_out);
+}
+
+cmhd_status do_cfl(cmhd_ctx* c, double* state, double* dt_out) {
+  cmhd_status st = do_fill(c, state);
+  if (st != CMHD_OK) return st;
+  return cfl_reduce(c, state, c->red, dt_out);
 }
 
 // event pair for one timed launch of kernel `which` (or none when not profiling)
@@ -400,9 +439,14 @@ cmhd_status cmhd_init_grid_z(const cmhd_grid* grid, const cmhd_params* params, c
                  prop.gcnArchName);
     return CMHD_EDEVICE;
   }
+  if (init_noalloc_scratch(dev) != hipSuccess) {
+    std::fprintf(stderr, "cmhd_init_grid: no address for the library's device scratch\n");
+    return CMHD_EDEVICE;
+  }
   cmhd_ctx* c = new cmhd_ctx();
   c->grid = g;
   c->par = q;
+  c->dev = dev;
   c->stream = (hipStream_t)stream;
   fill_kparams(c, lnrho0_z);
   fill_zgrid(c, z);
@@ -546,6 +590,18 @@ cmhd_status cmhd_cfl_dt(cmhd_ctx* c, double* state, double* dt_out) {
   cmhd_status st = need_ws(c);
   if (st != CMHD_OK) return st;
   return do_cfl(c, state, dt_out);
+}
+
+cmhd_status cmhd_cfl_dt_noalloc(cmhd_ctx* c, const double* state, double* dt_out) {
+  if (!c || !state || !dt_out) return CMHD_EINVAL;
+  if (c->kp.stretched && !c->ws)
+    return fail(c, CMHD_ESTATE, "a non-uniform z grid needs the bound workspace (its z table)");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != c->dev)
+    return fail(c, CMHD_ESTATE, "the context's GPU is not the current device");
+  unsigned long long* red = g_scratch[c->dev];
+  if (!red) return fail(c, CMHD_ESTATE, "no device scratch for this GPU");
+  return cfl_reduce(c, state, red, dt_out);
 }
 
 cmhd_status cmhd_rk3_step(cmhd_ctx* c, double* state, double* t, double dt, double* dt_used) {
