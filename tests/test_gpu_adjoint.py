@@ -221,6 +221,44 @@ def test_adjoint128_gradient_at_10mm():
     assert _gradient_and_fd(10.0, target, 1e-2, 8) <= 1e-3
 
 
+@pytest.mark.timeout(600)
+def test_adjoint128_gradient_against_oracle_complex_step():
+    # the adjoint box as configured: 128 x 128 x 64 with radiation and
+    # Spitzer conduction on, the B_z misfit on the plane z = 10 Mm after 20
+    # steps, checkpoints every 5.  The reference is the oracle's complex-step
+    # directional derivative along two seeded directions of u* (exact to
+    # round-off, no difference quotient), written by
+    # tests/golden/make_adjoint128_cs.py; the loss itself is checked too.
+    import json
+    import os
+
+    import torch
+    from paper_1908_08557_amd import adjoint as A
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "adjoint128_cs.json")))
+    w = W.adjoint128()
+    dt, nsteps, zq = gold["dt"], gold["nsteps"], gold["zq"]
+    print(f"[case] adjoint128 full physics, z={zq}, {nsteps} steps, dt={dt:.3e}", flush=True)
+    s = _solver(w)
+    x0 = s.new_state(w.state)
+    target = torch.as_tensor(w.extra["bz_target_z10"], device="cuda")
+    uh = torch.as_tensor(w.uh_target, device="cuda").clone().requires_grad_(True)
+    xn = A.rollout(s, x0, uh, 0.0, dt, nsteps, ckpt_every=5)
+    loss = A.bz_misfit_loss(s, xn, zq, target)
+    loss.backward()
+    lv = float(loss.detach())
+    print(f"[grad] loss {lv:.15e} oracle {gold['loss']:.15e}", flush=True)
+    assert abs(lv - gold["loss"]) <= 1e-11 * abs(gold["loss"])
+    grad = uh.grad.detach()
+    for d in gold["directions"]:
+        v = np.random.default_rng(d["seed"]).standard_normal(w.uh_target.shape)
+        got = float((grad * torch.as_tensor(v, device="cuda")).sum())
+        ref = d["dL_dv"]
+        print(f"[grad] direction seed {d['seed']}: adjoint {got:.15e} complex step {ref:.15e} "
+              f"rel {abs(got - ref) / abs(ref):.2e}", flush=True)
+        assert abs(got - ref) <= 1e-10 * abs(ref)
+
+
 @pytest.mark.parametrize("grid", ["uniform", "stretched"])
 def test_bz_plane_vjp_dot_product(grid):
     # B_z on a plane is affine in the state: <bz(x + dx) - bz(x), bzbar> must

@@ -12,7 +12,8 @@ import pytest
 
 from oracle import mhd as O
 from paper_1908_08557_amd import workloads as W
-from parity_util import GROUPS, NAMES, NG, oracle_patch_centre
+from parity_util import (FLOOR_FACTOR, GROUPS, NAMES, NG, RESIDUES, oracle_patch_centre,
+                         perturbed)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,18 +49,41 @@ def _samples(w, seed):
     return list(zip(ks, js, is_))
 
 
-def _check(w, got, dt, tol, label):
-    scales = []
-    for f in range(8):
-        scales.append(max(np.max(np.abs(got[q, NG:-NG])) for q in GROUPS[f]))
+def _check(w, got, dt, tol, label, precision):
+    """Sampled zones against the oracle, each component relative to its own
+    max norm over the box, the cancellation residues (and, in the split
+    form, the velocity one step from hydrostatic rest) relative to their
+    field.  In float64 a component is held to FLOOR_FACTOR times the
+    oracle's own spread where that exceeds tol: the patch is run again from
+    a state moved by one unit in the last place.  All figures printed."""
+    own = np.array([np.max(np.abs(got[f, NG:-NG])) for f in range(8)])
+    grp = np.array([max(own[q] for q in GROUPS[f]) for f in range(8)])
+    by_field = [NAMES[f] in RESIDUES or (precision != "fp64" and NAMES[f] in ("ux", "uy", "uz"))
+                for f in range(8)]
+    scales = np.array([grp[f] if by_field[f] else own[f] for f in range(8)])
+    wp = perturbed(w) if precision == "fp64" else None
     worst = np.zeros(8)
+    spread = np.zeros(8)
     for (k, j, i) in _samples(w, 11):
         ref = oracle_patch_centre(w, int(k), int(j), int(i), dt, H)
         val = got[:, NG + k, j, i]
-        worst = np.maximum(worst, np.abs(val - ref) / np.array(scales))
-    print(f"[parity] {label} sampled: " + " ".join(f"{NAMES[f]}={worst[f]:.2e}" for f in range(8)),
-          flush=True)
-    assert np.all(worst <= tol), (label, dict(zip(NAMES, worst)))
+        worst = np.maximum(worst, np.abs(val - ref))
+        if wp is not None:
+            refp = oracle_patch_centre(wp, int(k), int(j), int(i), dt, H)
+            spread = np.maximum(spread, np.abs(refp - ref))
+    print(f"[parity] {label} sampled own: "
+          + " ".join(f"{NAMES[f]}={worst[f] / own[f]:.2e}" for f in range(8)), flush=True)
+    print(f"[parity] {label} sampled field: "
+          + " ".join(f"{NAMES[f]}={worst[f] / grp[f]:.2e}" for f in range(8)), flush=True)
+    lim = np.full(8, tol)
+    if wp is not None:
+        print(f"[parity] {label} oracle floor: "
+              + " ".join(f"{NAMES[f]}={spread[f] / own[f]:.2e}" for f in range(8)), flush=True)
+        for f in range(8):
+            if not by_field[f]:
+                lim[f] = max(tol, FLOOR_FACTOR * spread[f] / own[f])
+    rel = worst / scales
+    assert np.all(rel <= lim), (label, dict(zip(NAMES, zip(rel, lim))))
 
 
 @pytest.mark.timeout(900)
@@ -68,7 +92,7 @@ def test_strat512_one_step_sampled(precision, tol):
     w = W.strat512()
     print(f"[case] strat512 one step {precision}, {NSAMPLE} sampled zones", flush=True)
     got, dt = _gpu_one_step(w, precision)
-    _check(w, got, dt, tol, f"strat512 {precision}")
+    _check(w, got, dt, tol, f"strat512 {precision}", precision)
 
 
 @pytest.mark.timeout(900)
@@ -77,7 +101,7 @@ def test_strat512_stretched_one_step_sampled(precision, tol):
     w = W.strat512_stretched()
     print(f"[case] strat512_stretched one step {precision}, {NSAMPLE} sampled zones", flush=True)
     got, dt = _gpu_one_step(w, precision)
-    _check(w, got, dt, tol, f"strat512_stretched {precision}")
+    _check(w, got, dt, tol, f"strat512_stretched {precision}", precision)
 
 
 @pytest.mark.timeout(1200)
@@ -87,4 +111,4 @@ def test_ar1024_one_step_sampled():
     w = W.ar1024()
     print(f"[case] ar1024 one step fp32_split, {NSAMPLE} sampled zones", flush=True)
     got, dt = _gpu_one_step(w, "fp32_split")
-    _check(w, got, dt, 2e-6, "ar1024 fp32_split")
+    _check(w, got, dt, 2e-6, "ar1024 fp32_split", "fp32_split")

@@ -8,7 +8,13 @@ import pytest
 
 from oracle import mhd as O
 from paper_1908_08557_amd import workloads as W
-from parity_util import NG, assert_parity, oracle_dt, oracle_run
+from parity_util import NG, assert_parity, oracle_dt, oracle_floor, oracle_run
+
+# the velocity of a stratified box one or two steps from hydrostatic rest is
+# the residual of the pressure gradient, gravity and the Lorentz force of a
+# potential field (J = 0 up to rounding); in the split form its error is the
+# float32 rounding of those terms, so it is measured against |u|
+SPLIT_SHORT_BY_FIELD = ("ux", "uy", "uz")
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +58,8 @@ def test_one_step(case):
     dt = oracle_dt(w)
     ref = oracle_run(w, 1, dt)
     got = gpu_run(w, 1, dt)
-    assert_parity(got, ref, w.grid["zbc"] == "solar", 1e-12, f"{case} 1 step")
+    assert_parity(got, ref, w.grid["zbc"] == "solar", 1e-12, f"{case} 1 step",
+                  floor=oracle_floor(w, 1, dt, ref))
 
 
 @pytest.mark.parametrize("case", ["periodic16", "strat32x32x24", "strat32x32x24_norad"])
@@ -62,7 +69,8 @@ def test_ten_steps(case):
     dt = oracle_dt(w)
     ref = oracle_run(w, 10, dt)
     got = gpu_run(w, 10, dt)
-    assert_parity(got, ref, w.grid["zbc"] == "solar", 1e-11, f"{case} 10 steps")
+    assert_parity(got, ref, w.grid["zbc"] == "solar", 1e-11, f"{case} 10 steps",
+                  floor=oracle_floor(w, 10, dt, ref))
 
 
 @pytest.mark.parametrize("t0", [0.03, 1.0])
@@ -73,14 +81,16 @@ def test_driver_ramp_times(t0):
     dt = oracle_dt(w)
     ref = oracle_run(w, 3, dt, t0=t0)
     got = gpu_run(w, 3, dt, t0=t0)
-    assert_parity(got, ref, True, 1e-12, f"ramp t0={t0}")
+    assert_parity(got, ref, True, 1e-12, f"ramp t0={t0}", floor=oracle_floor(w, 3, dt, ref, t0))
 
 
 def test_strat64_one_step():
     w = W.strat64()
     print("[case] strat64 one step", flush=True)
     dt = oracle_dt(w)
-    assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12, "strat64 1 step")
+    ref = oracle_run(w, 1, dt)
+    assert_parity(gpu_run(w, 1, dt), ref, True, 1e-12, "strat64 1 step",
+                  floor=oracle_floor(w, 1, dt, ref))
 
 
 def newton_case(nx=32, ny=32, nz=24, norad=False):
@@ -112,8 +122,9 @@ def test_newton_cooling_one_step(norad):
     w = newton_case(norad=norad)
     dt = oracle_dt(w)
     print(f"[case] Newtonian cooling one step (norad={norad}, dt={dt:.3e})", flush=True)
-    assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
-                  f"newton 1 step norad={norad}")
+    ref = oracle_run(w, 1, dt)
+    assert_parity(gpu_run(w, 1, dt), ref, True, 1e-12, f"newton 1 step norad={norad}",
+                  floor=oracle_floor(w, 1, dt, ref))
 
 
 def test_newton_cooling_ten_steps_and_split():
@@ -122,13 +133,16 @@ def test_newton_cooling_ten_steps_and_split():
     w = newton_case()
     print("[case] Newtonian cooling ten steps (FP64) and two steps (FP32-split)", flush=True)
     dt = oracle_dt(w)
-    assert_parity(gpu_run(w, 10, dt), oracle_run(w, 10, dt), True, 1e-11, "newton 10 steps")
+    ref = oracle_run(w, 10, dt)
+    assert_parity(gpu_run(w, 10, dt), ref, True, 1e-11, "newton 10 steps",
+                  floor=oracle_floor(w, 10, dt, ref))
     s = cmhd.solver_for(w, "fp32_split")
     st = s.new_state(w.state)
     t = 0.0
     for _ in range(2):
         t, _ = s.rk3_step(st, t, dt)
-    assert_parity(st.cpu().numpy(), oracle_run(w, 2, dt), True, 2e-6, "newton 2 steps split")
+    assert_parity(st.cpu().numpy(), oracle_run(w, 2, dt), True, 2e-6, "newton 2 steps split",
+                  field_norm=SPLIT_SHORT_BY_FIELD)
 
 
 def test_newton_cooling_dt_limit():
@@ -150,10 +164,10 @@ _PIPELINED = {}   # oracle result shared by the two precisions
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
 def test_pipelined_substage(precision):
-    # 256 x 256 x 32 (256 tiles, two z chunks): the substage runs its
-    # z-derivative pass on a second stream, chunk by chunk, overlapping the
-    # fused kernel.  FP64 against the oracle after two steps; the FP32-split
-    # form against the same oracle at its own tolerance.
+    # 256 x 256 x 32 (256 tiles, 8 z chunks of 4 planes: each block's z
+    # window starts and ends inside the box).  FP64 against the oracle after
+    # two steps; the FP32-split form against the same oracle at its own
+    # tolerance.
     import torch
     from paper_1908_08557_amd import cmhd
     w = W.small_stratified(256, 256, 32, Lxy=80.0, z1=20.0, nbip=4)
@@ -161,6 +175,7 @@ def test_pipelined_substage(precision):
     if "ref" not in _PIPELINED:
         _PIPELINED["dt"] = oracle_dt(w)
         _PIPELINED["ref"] = oracle_run(w, 2, _PIPELINED["dt"])
+        _PIPELINED["floor"] = oracle_floor(w, 2, _PIPELINED["dt"], _PIPELINED["ref"])
     dt = _PIPELINED["dt"]
     s = cmhd.solver_for(w, precision)
     st = s.new_state(w.state)
@@ -169,8 +184,12 @@ def test_pipelined_substage(precision):
         t, _ = s.rk3_step(st, t, dt)
     got = st.cpu().numpy()
     ref = _PIPELINED["ref"]
-    assert_parity(got, ref, True, 1e-12 if precision == "fp64" else 2e-6,
-                  f"pipelined 256x256x32 {precision}")
+    if precision == "fp64":
+        assert_parity(got, ref, True, 1e-12, "pipelined 256x256x32 fp64",
+                      floor=_PIPELINED["floor"])
+    else:
+        assert_parity(got, ref, True, 2e-6, "pipelined 256x256x32 fp32_split",
+                      field_norm=SPLIT_SHORT_BY_FIELD)
 
 
 @pytest.mark.timeout(900)
@@ -183,33 +202,25 @@ def test_strat64_hundred_steps():
     assert_parity(got, ref, True, 1e-10, "strat64 100 steps")
 
 
+@pytest.mark.timeout(600)
+def test_strat_norad_hundred_steps():
+    # radiation and conduction off: dt is advective (~1.4e-3, about 1.7e5
+    # times the step that radiation and conduction allow), so the 100 steps
+    # move the stratified box far more than the full-physics case does
+    w = CASES["strat32x32x24_norad"]()
+    print("[case] strat32x32x24_norad 100 steps", flush=True)
+    dt = oracle_dt(w)
+    ref = oracle_run(w, 100, dt)
+    assert_parity(gpu_run(w, 100, dt), ref, True, 1e-10, "strat32x32x24_norad 100 steps",
+                  floor=oracle_floor(w, 100, dt, ref))
+
+
 def test_periodic16_hundred_steps():
     w = W.periodic_box(16)
     print("[case] periodic16 100 steps", flush=True)
     dt = oracle_dt(w)
     assert_parity(gpu_run(w, 100, dt), oracle_run(w, 100, dt), False, 1e-10,
                   "periodic16 100 steps")
-
-
-def test_fill_ghosts_matches_oracle():
-    import torch
-    w = W.small_stratified(32, 16, 12)
-    rng = np.random.default_rng(5)
-    w.state[3:6, NG:-NG] = rng.standard_normal(w.state[3:6, NG:-NG].shape)
-    w.state[7, NG:-NG] += 0.1 * rng.standard_normal(w.state[7, NG:-NG].shape)
-    print("[case] fill_ghosts solar", flush=True)
-    s = _solver(w)
-    st = s.new_state(w.state)
-    s.fill_ghosts(st)
-    torch.cuda.synchronize()
-    got = st.cpu().numpy()
-    F = O.from_compact(w.state)
-    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
-    ref = O.to_compact(F)
-    for f in range(8):
-        scale = np.max(np.abs(ref[f]))
-        err = np.max(np.abs(got[f] - ref[f]))
-        assert err <= 1e-13 * scale, (f, err, scale)
 
 
 def test_cfl_dt_matches_oracle():
@@ -244,7 +255,8 @@ def test_set_driver_from_bz():
     w.params["tau_A"] = 1.0 / dt   # make the nudging visible in one step
     got = gpu_run_with_bz(w, bz, dt)
     ref = oracle_run(w, 1, dt)
-    assert_parity(got, ref, True, 1e-12, "nudging toward A_h* from B_z")
+    assert_parity(got, ref, True, 1e-12, "nudging toward A_h* from B_z",
+                  floor=oracle_floor(w, 1, dt, ref))
 
 
 def gpu_run_with_bz(w, bz, dt):
@@ -374,13 +386,14 @@ def test_collapsed_time_step_reported():
 @pytest.mark.parametrize("nx,nz", [(128, 37), (256, 37)])
 def test_ragged_z_chunks(nx, nz):
     # the last z chunk of the fused kernel is short: 128^2 x 37 marches
-    # chunks of 2 planes (19 chunks, the last of 1) in one launch; 256^2 x 37
-    # is pipelined in chunks of 16, 16 and 5 planes
+    # chunks of 2 planes (19 chunks, the last of 1); 256^2 x 37 chunks of 5
+    # planes (8 chunks, the last of 2)
     w = W.small_stratified(nx, nx, nz, Lxy=nx * 0.3, z1=20.0, nbip=2)
     dt = oracle_dt(w)
     print(f"[case] ragged z chunks {nx}x{nx}x{nz}", flush=True)
-    assert_parity(gpu_run(w, 1, dt), oracle_run(w, 1, dt), True, 1e-12,
-                  f"ragged {nx}x{nx}x{nz}")
+    ref = oracle_run(w, 1, dt)
+    assert_parity(gpu_run(w, 1, dt), ref, True, 1e-12, f"ragged {nx}x{nx}x{nz}",
+                  floor=oracle_floor(w, 1, dt, ref))
 
 
 def _rhs_case(name):
