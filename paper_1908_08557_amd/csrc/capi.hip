@@ -230,6 +230,8 @@ void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
   p.nc_dlrw = q.nc_lnrho_width;
   p.nc_z0 = q.nc_z_max - q.nc_z_width;
   p.nc_zw = q.nc_z_width;
+  p.nc_pi_dlrw = q.nc_lnrho_width > 0.0 ? M_PI / q.nc_lnrho_width : 0.0;
+  p.nc_pi_zw = q.nc_z_width > 0.0 ? M_PI / q.nc_z_width : 0.0;
   p.nc_lnrho_phot = lnrho0_z ? lnrho0_z[NG] : 0.0;
   p.nc_n = g.nz + 2 * NG;
   p.nc_tab = nullptr;   // set when the workspace is bound

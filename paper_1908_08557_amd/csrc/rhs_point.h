@@ -69,18 +69,19 @@ __device__ inline double s_sin(double a) { return sin(a); }
 __device__ inline double value_of(double a) { return a; }
 
 // 1 for x <= start, 0 for x >= start + width, 1/2 [1 - sin(pi (x - start -
-// width/2) / width)] between (the sine cutoffs of the Newtonian cooling)
+// width/2) / width)] between (the sine cutoffs of the Newtonian cooling);
+// pi_w = pi / width, formed on the host
 template <typename S>
-__device__ inline S sine_cutoff(S x, double start, double width) {
+__device__ inline S sine_cutoff(S x, double start, double width, double pi_w) {
   const double xv = value_of(x);
   if (xv <= start) return S(1.0);
   if (xv >= start + width) return S(0.0);
-  return S(0.5) * (S(1.0) - s_sin(S(M_PI / width) * (x - S(start + 0.5 * width))));
+  return S(0.5) * (S(1.0) - s_sin(S(pi_w) * (x - S(start + 0.5 * width))));
 }
 
 // height cutoff c_z of the Newtonian cooling at plane k (z_k = z0 + k dz)
 __device__ inline double nc_height_cut(const KParams& p, int k) {
-  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(zk(p, k), p.nc_z0, p.nc_zw);
+  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(zk(p, k), p.nc_z0, p.nc_zw, p.nc_pi_zw);
 }
 
 // the initial profiles of the Newtonian cooling through the kernel parameters
@@ -323,7 +324,7 @@ __device__ __forceinline__ S rhs_newton(const Src& src, const KParams& p, const 
     lT = src.v(LT);
   }
   const double xv = value_of(lr);
-  const T crho = sine_cutoff(T(p.nc_lnrho_phot) - lr, p.nc_dlr0, p.nc_dlrw);
+  const T crho = sine_cutoff(T(p.nc_lnrho_phot) - lr, p.nc_dlr0, p.nc_dlrw, p.nc_pi_dlrw);
   if (value_of(crho) == 0.0) return S(0.0);
   const int n = p.nc_n;
   T lTp;
@@ -418,25 +419,45 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S
 //   dlnrho = -u.grad ln rho - div u + (D_rho + chi_rho w) lap ln rho + D_rho |grad ln rho|^2
 //   dlnT   = -u.grad ln T - (gamma-1) div u + 2 rho nu S:S / (rho c_v T) - Q_rad/(rho c_v T)
 //            (+ Newtonian cooling)
-// with div u and S:S from rhs_momentum.
+// with div u and S:S from rhs_momentum.  In two pieces: rhs_scalars_pre needs
+// no velocity gradient (LRp, LTp the two equations without their div u and
+// S:S terms, cS = 2 nu / (c_v T) the factor of S:S), rhs_scalars_post adds
+// those terms.
 template <typename S, class Src>
-__device__ __forceinline__ void rhs_scalars(const Src& src, const PointCtx<S>& pc,
-                                            const KParams& p, S divu, S SS, S rad, S nc,
-                                            S out[NF]) {
+__device__ __forceinline__ void rhs_scalars_pre(const Src& src, const PointCtx<S>& pc,
+                                                const KParams& p, S nc, S& LRp, S& LTp,
+                                                S& cS) {
   const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   {
     const S Glr[3] = {src.d(LR, 0), src.d(LR, 1), src.d(LR, 2)};
     const S udr = u[0] * Glr[0] + u[1] * Glr[1] + u[2] * Glr[2];
     const S gr2 = Glr[0] * Glr[0] + Glr[1] * Glr[1] + Glr[2] * Glr[2];
-    out[LR] = (S(p.D_rho) + S(p.chi_rho) * S(pc.w)) * src.lapr() - udr - divu + S(p.D_rho) * gr2;
+    LRp = (S(p.D_rho) + S(p.chi_rho) * S(pc.w)) * src.lapr() - udr + S(p.D_rho) * gr2;
   }
   {
     S T;
     if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
     else T = s_exp(src.v(LT));
     const S udT = u[0] * src.d(LT, 0) + u[1] * src.d(LT, 1) + u[2] * src.d(LT, 2);
-    out[LT] = S(2.0) * S(p.nu) * SS / (S(p.cv) * T) - rad - udT - S(p.gm1) * divu + nc;
+    LTp = nc - udT;
+    cS = S(2.0) * S(p.nu) / (S(p.cv) * T);
   }
+}
+
+template <typename S>
+__device__ __forceinline__ void rhs_scalars_post(const KParams& p, S LRp, S LTp, S cS, S divu,
+                                                 S SS, S rad, S& dlr, S& dlT) {
+  dlr = LRp - divu;
+  dlT = cS * SS + LTp - rad - S(p.gm1) * divu;
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ void rhs_scalars(const Src& src, const PointCtx<S>& pc,
+                                            const KParams& p, S divu, S SS, S rad, S nc,
+                                            S out[NF]) {
+  S LRp, LTp, cS;
+  rhs_scalars_pre<S>(src, pc, p, nc, LRp, LTp, cS);
+  rhs_scalars_post<S>(p, LRp, LTp, cS, divu, SS, rad, out[LR], out[LT]);
 }
 
 // the fluid equations without the magnetic terms: momentum, continuity, energy

@@ -2,30 +2,37 @@
 // register update, with the z derivatives formed on chip from a sliding
 // window of each column (no z-derivative buffer in HBM).
 //
-// k_substage: one block of 512 threads (8 waves, two per SIMD) per 16 x 16
-// tile of columns and z chunk, marching in z.  Per plane k:
+// k_substage: one block of 1024 threads (16 waves, four per SIMD) per 16 x 16
+// tile of columns and z chunk, marching in z.  Waves 8-15 hold the z window,
+// waves 0-3 evaluate the magnetic part of the right-hand side, waves 4-7 the
+// fluid part.  Per plane k:
 //
 //   W  window: thread t < 484 owns column t of the 22 x 22 haloed tile and
-//      keeps the planes k-3 .. k+3 of all 8 fields in registers (loaded
-//      once per plane from HBM/L2, one plane ahead).  It writes to LDS the
-//      plane values f(k), the sixth-order d/dz on the haloed tile and, for
-//      the own columns, d2/dz2 (metric-scaled on a non-uniform grid).
-//   X  the right-hand-side waves form D1_x of the six fields with an xy
-//      mixed derivative (A, u_x, u_y, ln T) on the tile columns and all 22
-//      rows, and the pointwise loss terms of ln T (radiation, cooling).
+//      keeps the planes k-3 .. k+3 of all 8 fields in registers (each
+//      loaded once, from HBM/L2, during the previous plane).  It writes to
+//      LDS the plane values f(k), the sixth-order d/dz on the haloed tile
+//      and, for the own columns, d2/dz2 (metric-scaled on a non-uniform
+//      grid).
+//      Meanwhile the right-hand-side waves finish plane k-1 (F below).
+//   X  D1_x of the six fields with an xy mixed derivative (A, u_x, u_y,
+//      ln T) on the tile columns and all 22 rows, those of A by the window
+//      waves, which then load the next plane into their ring, the others
+//      by the right-hand-side waves, which also copy the RK register and f
+//      of the own tile into LDS and form the pointwise terms: the radiative
+//      loss (magnetic waves), the parts of continuity and energy without
+//      div u and S:S and the Newtonian cooling (fluid).
 //   R  right-hand side at the own columns, every derivative read from LDS
-//      on demand: waves 0-3 the magnetic part
-//      (induction, B, J, Spitzer conduction, Ohmic heating, the swamp
-//      diffusion of ln T) and the register update of A; waves 4-7 the
-//      momentum equation, div u and S:S.  Results go to LDS.
-//   F  the fluid waves form continuity and energy, add the magnetic terms
-//      (J x B / rho, heating of ln T), apply the boundary terms and update
-//      u, ln rho, ln T.
+//      on demand: the magnetic waves the induction equation, B, J, Spitzer
+//      conduction, Ohmic heating, the swamp diffusion of ln T and the Lorentz
+//      force; the fluid waves the momentum equation and the div u and S:S
+//      terms.  Results go to LDS.
+//   F  (during the next plane's W) from LDS only: the fluid waves add the
+//      magnetic terms and the boundary terms; both update their fields.
 //
-// Four barriers per plane (after W, after X, after R, after F).  The HBM
-// traffic is that of the 2N method itself: f read once (halo columns of
-// neighbouring tiles are shared through L2), dF read and written, f_next
-// written, 213 B per zone and substage on average.
+// Three barriers per plane (after W, after X, after R).  The HBM traffic is
+// that of the 2N method itself: f read once (halo columns of neighbouring
+// tiles are shared through L2; the own-column copy for F is an L2 hit), dF
+// read and written, f_next written, 213 B per zone and substage on average.
 //
 // Mixed derivatives are products of first-derivative stencils: xy as D1_y of
 // the staged D1_x, xz and yz as D1_x, D1_y of the staged d/dz.  Every
@@ -53,6 +60,7 @@ __host__ __device__ constexpr int dx_slot(int f) {
 }
 __host__ __device__ constexpr int dx_field(int s) { return s < 5 ? s : LT; }
 
+
 template <typename Real, bool NEWTON>
 struct Smem {
   double P[NF][HN];         // f(k) on the haloed tile
@@ -60,11 +68,12 @@ struct Smem {
   Real ZZ[NF][NT];          // d2/dz2 at the own columns
   double Dx[NDX][DXP];      // unscaled D1_x
   Real X[NXCH][NT];         // magnetic -> fluid
-  Real Q[7][NT];            // momentum RHS (3), div u, S:S, radiative loss, cooling
+  Real Q[7][NT];            // momentum RHS (3), d ln rho/dt, d ln T/dt (partial), radiative loss,
+                            // 2 nu/(c_v T)
   Real QA[3][NT];           // induction RHS
   double R[NF][NT];         // the RK register of the own columns (global->LDS copies)
+  double Fown[NF][NT];      // f at the own columns (global->LDS copies)
   double rad[3 * CMHD_MAX_RAD];
-  double nc[NEWTON ? 2 * CMHD_MAX_NC_TABLE : 1];
 };
 
 // An integer the compiler cannot see through, re-made at every plane, so that
@@ -73,6 +82,14 @@ struct Smem {
 __device__ __forceinline__ int opaque(int i) {
   asm volatile("" : "+v"(i));
   return i;
+}
+
+// A wave-uniform double the compiler re-reads from its scalar register at
+// each use (its conversion to float is then not hoisted into a vector
+// register held across the plane loop)
+__device__ __forceinline__ double sreg(double x) {
+  asm volatile("" : "+s"(x));
+  return x;
 }
 
 // Workgroup barrier for LDS traffic only: this wave's LDS reads and writes
@@ -109,6 +126,17 @@ __device__ __forceinline__ T d1s(const T* a, int s) {
   return T(45.0) * (a[s] - a[-s]) - T(9.0) * (a[2 * s] - a[-2 * s]) + (a[3 * s] - a[-3 * s]);
 }
 
+// the same first difference with at most two of its values in flight (the
+// window waves form it while they hold their z window in registers)
+template <typename T>
+__device__ __forceinline__ T d1s_lean(const T* a, int s) {
+  T acc = T(45.0) * (a[s] - a[-s]);
+  __builtin_amdgcn_sched_barrier(0);
+  acc = acc - T(9.0) * (a[2 * s] - a[-2 * s]);
+  __builtin_amdgcn_sched_barrier(0);
+  return acc + (a[3 * s] - a[-3 * s]);
+}
+
 // Global access at a wave-uniform base plus a 32-bit per-lane byte offset
 // (scalar base register + one offset register, no per-lane 64-bit pointers)
 // (the empty asm keeps the compiler from folding the offset into a 64-bit
@@ -131,12 +159,6 @@ struct LdsRadTable {
   __device__ __forceinline__ double lnL(int i) const { return t[CMHD_MAX_RAD + i]; }
   __device__ __forceinline__ double slope(int i) const { return t[2 * CMHD_MAX_RAD + i]; }
 };
-struct LdsNcTable {
-  const double* t;   // [ln rho0 (n)][ln T0 (n)]
-  int n;
-  __device__ __forceinline__ double lnrho0(int i) const { return t[i]; }
-  __device__ __forceinline__ double lnT0(int i) const { return t[n + i]; }
-};
 
 // Source of the pointwise right-hand side: every value and derivative read
 // from LDS on demand.  Bases are per-thread (tile origin of the own column)
@@ -157,17 +179,6 @@ struct LdsSrc {
     if (dir == 0) return Real(d1s(a, 1) * i60dx);
     if (dir == 1) return Real(d1s(a, HW) * i60dy);
     return Z[f * HN + OWN];
-  }
-  __device__ __forceinline__ Real h(int f, int s) const {
-    const double* a = P + f * HN + OWN;
-    switch (s) {
-      case 0: return Real(d2x(a) * i180dx2);
-      case 1: return Real(d2y(a) * i180dy2);
-      case 2: return ZZ[f * NT];
-      case 3: return dx_slot(f) >= 0 ? Real(d1s(Dx + dx_slot(f) * DXP + DOWN, TX) * ixy) : Real(0);
-      case 4: return d1s(Z + f * HN + OWN, 1) * Real(i60dx);
-      default: return d1s(Z + f * HN + OWN, HW) * Real(i60dy);
-    }
   }
   __device__ __forceinline__ static double d2x(const double* a) {
     return -490.0 * a[0] + 270.0 * (a[1] + a[-1]) - 27.0 * (a[2] + a[-2]) +
@@ -205,6 +216,14 @@ struct LdsSrc {
     const double* a = P + LR * HN + OWN;
     return Real(d2x(a) * i180dx2 + d2y(a) * i180dy2 + double(ZZ[LR * NT]));
   }
+};
+
+// f at the own column, from the LDS copy (the boundary terms of F)
+template <typename Real>
+struct OwnSrc {
+  const double* F;    // + f*NT: own column
+  __device__ __forceinline__ Real v(int f) const { return Real(F[f * NT]); }
+  __device__ __forceinline__ double v64(int f) const { return F[f * NT]; }
 };
 
 // Block -> (tile x, tile y, z chunk).  Blocks are dispatched round-robin to
@@ -265,6 +284,26 @@ __device__ __forceinline__ void zmetric(const KParams& p, int k, double& c1, dou
   c3 = t[zt_c3(p) + k];
 }
 
+// D1_x (unscaled) of the xy-mixed fields on the tile columns and all 22 rows
+// of the staged plane (the right-hand side reads it for the xy mixed
+// derivatives), between the first and second barrier: the window waves form
+// the slots [0, NDX/2) with at most two values in flight (they hold their z
+// window meanwhile), the right-hand-side waves the rest.  t is the thread's
+// index within its group of 512.
+constexpr int NDXH = NDX / 2 * DXP;   // items per group
+template <typename Real, bool NEWTON, bool WINDOW>
+__device__ __forceinline__ void stencils_dx(Smem<Real, NEWTON>& sm, int t) {
+  // (opaque: the per-item indices are re-derived at every plane, not held
+  // in registers across the plane loop)
+#pragma unroll 1
+  for (int i = opaque(t); i < NDXH; i += NT2) {
+    const int s = i / DXP + (WINDOW ? 0 : NDX / 2), pt = i - (i / DXP) * DXP;
+    const int row = pt / TX, col = pt - row * TX;
+    const double* a = &sm.P[dx_field(s)][row * HW + col + NG];
+    sm.Dx[s][pt] = WINDOW ? d1s_lean(a, 1) : d1s(a, 1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The window waves (8..15): W and X of every plane.  Each thread keeps the
 // planes k-3 .. k+3 of its column in a ring of registers; the loop is unrolled
@@ -300,10 +339,6 @@ __device__ __forceinline__ void window_loop(Smem<Real, NEWTON>& sm, const double
     constexpr int r = decltype(rc)::value;
     double c1, c2, c3;
     zmetric(p, k, c1, c2, c3);
-    // the next plane's values are loaded now and consumed at the next plane
-    // (the last plane reloads a plane it already holds: the load is
-    // unconditional)
-    const double* fn = f + (k + 1 < kend ? k + 7 : k + 6) * sp;
 #pragma unroll
     for (int fi = 0; fi < NF; ++fi) {
       const double q0 = w[fi][r % 7], q1 = w[fi][(r + 1) % 7], q2 = w[fi][(r + 2) % 7];
@@ -316,12 +351,19 @@ __device__ __forceinline__ void window_loop(Smem<Real, NEWTON>& sm, const double
         sm.Z[fi][wt] = Real(s1 * c1);
       }
       if (wown) sm.ZZ[fi][wo] = Real(s2 * c2 + s1 * c3);
-      w[fi][r] = ld_u(fn + fi * sf, wc);
     }
     lds_barrier();   // B1: the plane is staged
-    lds_barrier();   // B2: D1_x staged; the RHS waves work on the plane
-    lds_barrier();   // B3: right-hand sides done
-    lds_barrier();   // B4: the staged plane is no longer read
+    // the stencils while the slot of plane k-3 is free, then the next
+    // plane's values into it (consumed at the next plane; the last plane
+    // reloads a plane it already holds: the load is unconditional)
+    stencils_dx<Real, NEWTON, true>(sm, wt);
+    {
+      const double* fn = f + (k + 1 < kend ? k + 7 : k + 6) * sp;
+#pragma unroll
+      for (int fi = 0; fi < NF; ++fi) w[fi][r] = ld_u(fn + fi * sf, wc);
+    }
+    lds_barrier();   // B2: the stencils are staged; the RHS waves work on the plane
+    lds_barrier();   // B3: right-hand sides done, the staged plane is no longer read
   };
   for (int k = kbeg; k < kend; k += 7) {
     plane(std::integral_constant<int, 0>{}, k);
@@ -375,11 +417,10 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
     sm.rad[CMHD_MAX_RAD + tid] = p.rad_lnL[tid];
     sm.rad[2 * CMHD_MAX_RAD + tid] = p.rad_slope[tid];
   }
-  if (NEWTON)
-    for (int i = tid; i < 2 * p.nc_n; i += NT2) sm.nc[i] = p.nc_tab[i];
 
-  // this wave's share of the RK-register copies: wave w copies field w, two
-  // 16-byte chunks per lane (a 16 x 16 tile row is 8 chunks)
+  // this wave's share of the copies of the RK register and of f at the own
+  // tile: wave w copies field w, two 16-byte chunks per lane (a 16 x 16 tile
+  // row is 8 chunks)
   const int cw = wave;
   unsigned coff[2];
 #pragma unroll
@@ -388,43 +429,119 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
     coff[m] = unsigned((y0 + ch / 8) * p.nx + x0 + (ch % 8) * 2) * 8u;
   }
 
+  // F of plane kf: the register updates, from LDS only (the right-hand sides,
+  // the copied RK register and f), so that it runs while the window waves
+  // stage the next plane.  The magnetic waves update A (with the photospheric
+  // nudging); the fluid waves add the magnetic terms, apply the boundary
+  // terms and update u, ln rho, ln T.
+  auto finish = [&](int kf) {
+    const long long pl = (kf + NG) * sp;
+    const int oo = opaque(o);
+    const OwnSrc<Real> own{&sm.Fown[0][0] + oo};
+    PointCtx<Real> pc;
+    pc.bottom = SOLAR && kf == 0;
+    pc.top = SOLAR && kf == p.nz - 1;
+    pc.ramp = st.ramp;
+    if (mag) {
+      Real out[NF];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) out[AX + i] = sm.QA[i][oo];
+      if (SOLAR && kf == 0) {
+        pc.ah[0] = Real(ld_u(ah, oc));
+        pc.ah[1] = Real(ld_u(ah + sp, oc));
+        rhs_boundary_magnetic<Real>(own, pc, p, out);
+      }
+      // 2N-RK3 update of A in float64
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int fi = AX + i;
+        const double r = double(out[fi]);
+        const double d = READ_DF ? st.alpha * sm.R[fi][oo] + st.dt * r : st.dt * r;
+        if (WRITE_DF) st_u(dF + fi * sf + pl, oc, d);
+        st_u(fo + fi * sf + pl, oc, own.v64(fi) + st.beta * d);
+      }
+    } else {
+      Real out[NF];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) out[UX + i] = sm.Q[i][oo];
+      out[LR] = sm.Q[3][oo];
+      out[LT] = sm.Q[4][oo];
+      {
+        Real add[NXCH];
+#pragma unroll
+        for (int i = 0; i < NXCH; ++i) add[i] = sm.X[i][oo];
+        rhs_add_magnetic<Real>(add, out);
+      }
+      if (SOLAR && kf == 0) {
+        pc.uh[0] = Real(ld_u(uh, oc));
+        pc.uh[1] = Real(ld_u(uh + sp, oc));
+      }
+      rhs_boundary_fluid<Real>(own, pc, p, out);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const int fi = UX + i;
+        const double r = double(out[fi]);
+        double d = READ_DF ? st.alpha * sm.R[fi][oo] + st.dt * r : st.dt * r;
+        double fnew = own.v64(fi) + st.beta * d;
+        if (SOLAR) {
+          // closed boundary (u_z = 0 at both boundary planes) and the
+          // photospheric density held at its initial value ('fg')
+          const bool fixz = (fi == UZ) && (kf == 0 || kf == p.nz - 1);
+          const bool fixr = (fi == LR) && (kf == 0);
+          if (fixz || fixr) {
+            d = 0.0;
+            fnew = fixr ? p.lnrho0_bot[3] : 0.0;
+          }
+        }
+        if (WRITE_DF) st_u(dF + fi * sf + pl, oc, d);
+        st_u(fo + fi * sf + pl, oc, fnew);
+      }
+    }
+  };
+
   for (int k = kbeg; k < kend; ++k) {
     const long long pl = (k + NG) * sp;
+    // ---- F of the previous plane (the window waves stage this one)
+    if (k > kbeg) finish(k - 1);
+    lds_barrier();     // B1: the plane is staged; the previous plane's F reads are done
     const int oo = opaque(o);   // own column for the direct LDS accesses of this plane
-    // ---- the RK register of the own tile into LDS, in flight during W and X
-    if (READ_DF) {
+    // ---- the RK register and f of the own tile into LDS, in flight during X
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        unsigned off = coff[m];
-        asm volatile("" : "+v"(off));
+    for (int m = 0; m < 2; ++m) {
+      unsigned off = coff[m];
+      asm volatile("" : "+v"(off));
+      if (READ_DF)
         copy16(reinterpret_cast<const char*>(dF + cw * sf + pl) + off, &sm.R[cw][m * 128]);
-      }
+      copy16(reinterpret_cast<const char*>(f + cw * sf + pl) + off, &sm.Fown[cw][m * 128]);
     }
-    lds_barrier();     // B1: the plane is staged
-    // ---- X: D1_x (unscaled) of the xy-mixed fields on the tile columns and
-    // all 22 rows
-    for (int i = tid; i < NDX * DXP; i += NT2) {
-      const int s = i / DXP, pt = i - s * DXP;
-      const int row = pt / TX, col = pt - row * TX;
-      sm.Dx[s][pt] = d1s(&sm.P[dx_field(s)][row * HW + col + NG], 1);
-    }
-    // the pointwise loss terms of ln T (values only): radiative loss on the
-    // magnetic waves, Newtonian cooling on the fluid waves
+    // ---- X: D1_x of the xy-mixed fields (with the window waves), the
+    // radiative loss on the magnetic waves; the parts of continuity and
+    // energy without div u and S:S (and the Newtonian cooling) on the fluid
+    // waves
+    stencils_dx<Real, NEWTON, false>(sm, tid);
     {
-      const int io = opaque(ty * HW + tx);
-      const LdsSrc<Real> src{&sm.P[0][0] + io, &sm.Z[0][0] + io, &sm.ZZ[0][0],
-                             &sm.Dx[0][0], 0.0, 0.0, 0.0, 0.0, 0.0};
+      const int io = opaque(ty * HW + tx), iz = opaque(o);
+      const LdsSrc<Real> src{&sm.P[0][0] + io, &sm.Z[0][0] + io, &sm.ZZ[0][0] + iz,
+                             &sm.Dx[0][0], p.i60dx, p.i60dy, p.i180dx2, p.i180dy2, 0.0};
       if (mag) {
         sm.Q[5][oo] = rhs_radiation<Real>(src, p, LdsRadTable{sm.rad});
-      } else if (NEWTON) {
+      } else {
         PointCtx<Real> pc;
-        pc.nc_cz = nc_height_cut(p, k);
-        pc.nc_lnT0 = sm.nc[p.nc_n + k + NG];
-        sm.Q[6][oo] = rhs_newton<Real>(src, p, LdsNcTable{sm.nc, p.nc_n}, pc);
+        swamp(p, k, pc.w, pc.dw);
+        Real nc = Real(0.0);
+        if (NEWTON) {
+          pc.nc_cz = nc_height_cut(p, k);
+          pc.nc_lnT0 = p.nc_tab[p.nc_n + k + NG];
+          nc = rhs_newton<Real>(src, p, ParamNcTable{p}, pc);
+        }
+        Real LRp, LTp, cS;
+        rhs_scalars_pre<Real>(src, pc, p, nc, LRp, LTp, cS);
+        sm.Q[3][oo] = LRp;
+        sm.Q[4][oo] = LTp;
+        sm.Q[6][oo] = cS;
       }
     }
-    if (READ_DF) copies_barrier();   // B2: D1_x staged, the RK-register copies landed
-    else lds_barrier();
+    copies_barrier();  // B2: D1_x and the pointwise terms staged, the copies landed
 
     // ---- R: right-hand side at the own column
     const int io = opaque(ty * HW + tx), ixo = opaque(ty * TX + tx), iz = opaque(o);
@@ -433,12 +550,6 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
                            p.i60dx * p.i60dy};
     PointCtx<Real> pc;
     swamp(p, k, pc.w, pc.dw);
-    pc.bottom = SOLAR && k == 0;
-    pc.top = SOLAR && k == p.nz - 1;
-    pc.ramp = st.ramp;
-    pc.nc_cz = NEWTON ? nc_height_cut(p, k) : 0.0;
-    pc.nc_lnT0 = NEWTON ? sm.nc[p.nc_n + k + NG] : 0.0;
-    pc.uh[0] = pc.uh[1] = pc.ah[0] = pc.ah[1] = Real(0.0);
     if (mag) {
       Real out[NF];
       MagState<Real> m;
@@ -457,73 +568,15 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
       rhs_momentum<Real>(src, p, out, divu, SS);
 #pragma unroll
       for (int i = 0; i < 3; ++i) sm.Q[i][oo] = out[UX + i];
-      sm.Q[3][oo] = divu;
-      sm.Q[4][oo] = SS;
+      Real dlr, dlT;
+      rhs_scalars_post<Real>(p, sm.Q[3][oo], sm.Q[4][oo], sm.Q[6][oo], divu, SS, sm.Q[5][oo],
+                             dlr, dlT);
+      sm.Q[3][oo] = dlr;
+      sm.Q[4][oo] = dlT;
     }
-    lds_barrier();     // B3
-
-    // ---- F: the register updates, from LDS only (nothing is carried in
-    // registers across the barriers).  The magnetic waves update A (with the
-    // photospheric nudging); the fluid waves form continuity and energy, add
-    // the magnetic terms, apply the boundary terms and update u, ln rho, ln T.
-    if (mag) {
-      Real out[NF];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) out[AX + i] = sm.QA[i][oo];
-      if (SOLAR && k == 0) {
-        pc.ah[0] = Real(ld_u(ah, oc));
-        pc.ah[1] = Real(ld_u(ah + sp, oc));
-        rhs_boundary_magnetic<Real>(src, pc, p, out);
-      }
-      // 2N-RK3 update of A in float64
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int fi = AX + i;
-        const double r = double(out[fi]);
-        const double d = READ_DF ? st.alpha * sm.R[fi][oo] + st.dt * r : st.dt * r;
-        if (WRITE_DF) st_u(dF + fi * sf + pl, oc, d);
-        st_u(fo + fi * sf + pl, oc, src.v64(fi) + st.beta * d);
-      }
-    } else {
-      Real out[NF];
-      rhs_scalars<Real>(src, pc, p, sm.Q[3][oo], sm.Q[4][oo], sm.Q[5][oo],
-                        NEWTON ? sm.Q[6][oo] : Real(0.0), out);
-      CMHD_FENCE();
-#pragma unroll
-      for (int i = 0; i < 3; ++i) out[UX + i] = sm.Q[i][oo];
-      {
-        Real add[NXCH];
-#pragma unroll
-        for (int i = 0; i < NXCH; ++i) add[i] = sm.X[i][oo];
-        rhs_add_magnetic<Real>(add, out);
-      }
-      if (SOLAR && k == 0) {
-        pc.uh[0] = Real(ld_u(uh, oc));
-        pc.uh[1] = Real(ld_u(uh + sp, oc));
-      }
-      rhs_boundary_fluid<Real>(src, pc, p, out);
-#pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const int fi = UX + i;
-        const double r = double(out[fi]);
-        double d = READ_DF ? st.alpha * sm.R[fi][oo] + st.dt * r : st.dt * r;
-        double fnew = src.v64(fi) + st.beta * d;
-        if (SOLAR) {
-          // closed boundary (u_z = 0 at both boundary planes) and the
-          // photospheric density held at its initial value ('fg')
-          const bool fixz = (fi == UZ) && (k == 0 || k == p.nz - 1);
-          const bool fixr = (fi == LR) && (k == 0);
-          if (fixz || fixr) {
-            d = 0.0;
-            fnew = fixr ? p.lnrho0_bot[3] : 0.0;
-          }
-        }
-        if (WRITE_DF) st_u(dF + fi * sf + pl, oc, d);
-        st_u(fo + fi * sf + pl, oc, fnew);
-      }
-    }
-    lds_barrier();     // B4: the staged plane and the RK register are free
+    lds_barrier();     // B3: right-hand sides done; the staged plane is free
   }
+  finish(kend - 1);
 }
 
 // The u_x, u_y rows of the three lower ghost planes evolve under the nudging
