@@ -138,6 +138,9 @@ struct QSource {
     return slot >= 0 ? q(slot) : Dual(0.0);
   }
   __device__ Dual lapr() const { return q(Q_LAPR); }
+  __device__ void grad(int f, Dual g[3]) const {
+    for (int i = 0; i < 3; ++i) g[i] = d(f, i);
+  }
   __device__ void gh(int f, Dual g[3], Dual hh[6]) const {
     for (int i = 0; i < 3; ++i) g[i] = d(f, i);
     for (int s = 0; s < 6; ++s) hh[s] = h(f, s);

@@ -230,6 +230,10 @@ void fill_kparams(cmhd_ctx* c, const double* lnrho0_z) {
   p.nc_dlrw = q.nc_lnrho_width;
   p.nc_z0 = q.nc_z_max - q.nc_z_width;
   p.nc_zw = q.nc_z_width;
+  p.nc_dlr1 = p.nc_dlr0 + p.nc_dlrw;
+  p.nc_dlrm = p.nc_dlr0 + 0.5 * p.nc_dlrw;
+  p.nc_z1 = p.nc_z0 + p.nc_zw;
+  p.nc_zm = p.nc_z0 + 0.5 * p.nc_zw;
   p.nc_pi_dlrw = q.nc_lnrho_width > 0.0 ? M_PI / q.nc_lnrho_width : 0.0;
   p.nc_pi_zw = q.nc_z_width > 0.0 ? M_PI / q.nc_z_width : 0.0;
   p.nc_lnrho_phot = lnrho0_z ? lnrho0_z[NG] : 0.0;

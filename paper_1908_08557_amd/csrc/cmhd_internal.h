@@ -43,10 +43,11 @@ struct KParams {
   double c_adv, c_diff, c_nudge;
   // chromospheric Newtonian cooling: rate, start and width of the density
   // cutoff (in natural-log orders below ln rho0 at z0), of the height cutoff,
-  // the photospheric ln rho0, pi over the two cutoff widths, the table
-  // length (nz+6) and the device copy of the initial profiles
-  // [ln rho0 (nc_n) | ln T0 (nc_n)]
-  double nc_tau, nc_dlr0, nc_dlrw, nc_z0, nc_zw, nc_lnrho_phot, nc_pi_dlrw, nc_pi_zw;
+  // the photospheric ln rho0, the ends and middles of the two cutoffs and
+  // pi over their widths, the table length (nz+6) and the device copy of
+  // the initial profiles [ln rho0 (nc_n) | ln T0 (nc_n)]
+  double nc_tau, nc_dlr0, nc_dlrw, nc_z0, nc_zw, nc_lnrho_phot;
+  double nc_dlr1, nc_dlrm, nc_z1, nc_zm, nc_pi_dlrw, nc_pi_zw;
   int nc_n;
   const double* nc_tab;
   // non-uniform z grid (stretched != 0; uniform grids use z0 + k dz):

@@ -25,7 +25,8 @@
 // (G, H gradient and Hessian of ln T, b = B/|B|_r), and Q_rad = rho^2 Lambda(T) W(T).
 //
 // Source interface (f a field index, slot a Hessian slot xx yy zz xy xz yz):
-//   S v(f); double v64(f); S d(f, dir); S h(f, slot); S lapr();
+//   S v(f); double v64(f); S d(f, dir); S lapr();
+//   void grad(f, S g[3]): the gradient of f;
 //   void gh(f, S g[3], S h[6]): gradient and Hessian of f together (only the
 //   Hessian slots the equations use need be filled);
 //   kUnrollA, kUnrollU: unroll factors of the component loops over A and u
@@ -68,20 +69,21 @@ __device__ inline float s_sqrt(float a) { return __fsqrt_rn(a); }
 __device__ inline double s_sin(double a) { return sin(a); }
 __device__ inline double value_of(double a) { return a; }
 
-// 1 for x <= start, 0 for x >= start + width, 1/2 [1 - sin(pi (x - start -
-// width/2) / width)] between (the sine cutoffs of the Newtonian cooling);
-// pi_w = pi / width, formed on the host
+// 1 for x <= start, 0 for x >= end = start + width, 1/2 [1 - sin(pi (x -
+// mid) / width)] between, mid = start + width/2 (the sine cutoffs of the
+// Newtonian cooling); end, mid and pi_w = pi / width are formed on the host
 template <typename S>
-__device__ inline S sine_cutoff(S x, double start, double width, double pi_w) {
+__device__ inline S sine_cutoff(S x, double start, double end, double mid, double pi_w) {
   const double xv = value_of(x);
   if (xv <= start) return S(1.0);
-  if (xv >= start + width) return S(0.0);
-  return S(0.5) * (S(1.0) - s_sin(S(pi_w) * (x - S(start + 0.5 * width))));
+  if (xv >= end) return S(0.0);
+  return S(0.5) * (S(1.0) - s_sin(S(pi_w) * (x - S(mid))));
 }
 
 // height cutoff c_z of the Newtonian cooling at plane k (z_k = z0 + k dz)
 __device__ inline double nc_height_cut(const KParams& p, int k) {
-  return p.nc_tau == 0.0 ? 0.0 : sine_cutoff(zk(p, k), p.nc_z0, p.nc_zw, p.nc_pi_zw);
+  return p.nc_tau == 0.0 ? 0.0
+                         : sine_cutoff(zk(p, k), p.nc_z0, p.nc_z1, p.nc_zm, p.nc_pi_zw);
 }
 
 // the initial profiles of the Newtonian cooling through the kernel parameters
@@ -141,20 +143,25 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   for (int c = 0; c < 3; ++c) {
     S g[3], h[6];
     src.gh(AX + c, g, h);
-    const S gc = c == 0 ? g[0] : (c == 1 ? g[1] : g[2]);
-    divA = divA + gc;
-    B[0] = B[0] + (c == AZ ? g[1] : (c == AY ? -g[2] : S(0.0)));
-    B[1] = B[1] + (c == AX ? g[2] : (c == AZ ? -g[0] : S(0.0)));
-    B[2] = B[2] + (c == AY ? g[0] : (c == AX ? -g[1] : S(0.0)));
+    // 0/1 weights of this component (uniform across the wave): the
+    // accumulations are multiply-adds by them, which add exact zeros to the
+    // entries the component does not reach (no per-lane selects in a rolled
+    // loop)
+    const S e0 = S(c == 0 ? 1.0 : 0.0), e1 = S(c == 1 ? 1.0 : 0.0), e2 = S(c == 2 ? 1.0 : 0.0);
+    divA = divA + (g[0] * e0 + g[1] * e1 + g[2] * e2);
+    B[0] = B[0] + (g[1] * e2 - g[2] * e1);
+    B[1] = B[1] + (g[2] * e0 - g[0] * e2);
+    B[2] = B[2] + (g[0] * e1 - g[1] * e0);
     const S lap = h[0] + h[1] + h[2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) lapA[i] = (i == c) ? lap : lapA[i];
+    lapA[0] = lapA[0] + lap * e0;
+    lapA[1] = lapA[1] + lap * e1;
+    lapA[2] = lapA[2] + lap * e2;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const S hj0 = h[hslot(j, 0)], hj1 = h[hslot(j, 1)], hj2 = h[hslot(j, 2)];
-      dB[0][j] = dB[0][j] + (c == AY ? -hj2 : (c == AZ ? hj1 : S(0.0)));
-      dB[1][j] = dB[1][j] + (c == AX ? hj2 : (c == AZ ? -hj0 : S(0.0)));
-      dB[2][j] = dB[2][j] + (c == AX ? -hj1 : (c == AY ? hj0 : S(0.0)));
+      dB[0][j] = dB[0][j] + (hj1 * e2 - hj2 * e1);
+      dB[1][j] = dB[1][j] + (hj2 * e0 - hj0 * e2);
+      dB[2][j] = dB[2][j] + (hj0 * e1 - hj1 * e0);
     }
   }
 #pragma unroll
@@ -324,7 +331,8 @@ __device__ __forceinline__ S rhs_newton(const Src& src, const KParams& p, const 
     lT = src.v(LT);
   }
   const double xv = value_of(lr);
-  const T crho = sine_cutoff(T(p.nc_lnrho_phot) - lr, p.nc_dlr0, p.nc_dlrw, p.nc_pi_dlrw);
+  const T crho = sine_cutoff(T(p.nc_lnrho_phot) - lr, p.nc_dlr0, p.nc_dlr1, p.nc_dlrm,
+                               p.nc_pi_dlrw);
   if (value_of(crho) == 0.0) return S(0.0);
   const int n = p.nc_n;
   T lTp;
@@ -363,7 +371,9 @@ template <typename S, class Src>
 __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S out[NF],
                                              S& divu_out, S& SS_out) {
   const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
-  const S Glr[3] = {src.d(LR, 0), src.d(LR, 1), src.d(LR, 2)};
+  S Glr[3], GlT[3];
+  src.grad(LR, Glr);
+  src.grad(LT, GlT);
   S mom[3], divu = S(0.0), sq = S(0.0), cross = S(0.0);
   S a01 = S(0.0), a02 = S(0.0), a12 = S(0.0);   // a_01, a_02, a_12 for the cross sum
   {
@@ -372,7 +382,7 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S
     else T = s_exp(src.v(LT));
     const S RT = S(p.R) * T;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) mom[i] = -RT * (Glr[i] + src.d(LT, i));
+    for (int i = 0; i < 3; ++i) mom[i] = -RT * (Glr[i] + GlT[i]);
   }
 #pragma unroll(Src::kUnrollU)
   for (int c = 0; c < 3; ++c) {
@@ -382,17 +392,21 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S
     // selects so that a rolled loop indexes no register array)
     const S own = -(u[0] * g[0] + u[1] * g[1] + u[2] * g[2]) +
                   S(p.nu) * (h[0] + h[1] + h[2] + g[0] * Glr[0] + g[1] * Glr[1] + g[2] * Glr[2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) mom[i] = mom[i] + (i == c ? own : S(0.0));
+    // 0/1 weights of this component (uniform across the wave), as in
+    // rhs_magnetic: multiply-adds instead of per-lane selects
+    const S e0 = S(c == 0 ? 1.0 : 0.0), e1 = S(c == 1 ? 1.0 : 0.0), e2 = S(c == 2 ? 1.0 : 0.0);
+    mom[0] = mom[0] + own * e0;
+    mom[1] = mom[1] + own * e1;
+    mom[2] = mom[2] + own * e2;
     // grad div u: d_i d_c u_c (Hessian column c), and a_ci G_c into component i
-    const S Gc = c == 0 ? Glr[0] : (c == 1 ? Glr[1] : Glr[2]);
-    const S hc[3] = {c == 0 ? h[0] : (c == 1 ? h[3] : h[4]),
-                     c == 0 ? h[3] : (c == 1 ? h[1] : h[5]),
-                     c == 0 ? h[4] : (c == 1 ? h[5] : h[2])};
+    const S Gc = Glr[0] * e0 + Glr[1] * e1 + Glr[2] * e2;
+    const S hc[3] = {h[0] * e0 + h[3] * e1 + h[4] * e2,
+                     h[3] * e0 + h[1] * e1 + h[5] * e2,
+                     h[4] * e0 + h[5] * e1 + h[2] * e2};
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       mom[i] = mom[i] + S(p.nu) * (hc[i] * S(1.0 / 3.0) + g[i] * Gc);
-    divu = divu + (c == 0 ? g[0] : (c == 1 ? g[1] : g[2]));
+    divu = divu + (g[0] * e0 + g[1] * e1 + g[2] * e2);
     sq = sq + (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     // a_ij a_ji: the diagonal now, the off-diagonal pairs as their second member arrives
     if (c == 0) {
@@ -429,7 +443,8 @@ __device__ __forceinline__ void rhs_scalars_pre(const Src& src, const PointCtx<S
                                                 S& cS) {
   const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   {
-    const S Glr[3] = {src.d(LR, 0), src.d(LR, 1), src.d(LR, 2)};
+    S Glr[3];
+    src.grad(LR, Glr);
     const S udr = u[0] * Glr[0] + u[1] * Glr[1] + u[2] * Glr[2];
     const S gr2 = Glr[0] * Glr[0] + Glr[1] * Glr[1] + Glr[2] * Glr[2];
     LRp = (S(p.D_rho) + S(p.chi_rho) * S(pc.w)) * src.lapr() - udr + S(p.D_rho) * gr2;
@@ -438,7 +453,9 @@ __device__ __forceinline__ void rhs_scalars_pre(const Src& src, const PointCtx<S
     S T;
     if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
     else T = s_exp(src.v(LT));
-    const S udT = u[0] * src.d(LT, 0) + u[1] * src.d(LT, 1) + u[2] * src.d(LT, 2);
+    S GlT[3];
+    src.grad(LT, GlT);
+    const S udT = u[0] * GlT[0] + u[1] * GlT[1] + u[2] * GlT[2];
     LTp = nc - udT;
     cS = S(2.0) * S(p.nu) / (S(p.cv) * T);
   }

@@ -180,6 +180,18 @@ struct LdsSrc {
     if (dir == 1) return Real(d1s(a, HW) * i60dy);
     return Z[f * HN + OWN];
   }
+  // the gradient of f, its reads issued together and waited for once
+  __device__ __forceinline__ void grad(int f, Real g[3]) const {
+    const double* a = P + f * HN + OWN;
+    const double p1 = a[1], m1 = a[-1], p2 = a[2], m2 = a[-2], p3 = a[3], m3 = a[-3];
+    const double q1 = a[HW], n1 = a[-HW], q2 = a[2 * HW], n2 = a[-2 * HW], q3 = a[3 * HW],
+                 n3 = a[-3 * HW];
+    const Real zc = Z[f * HN + OWN];
+    __builtin_amdgcn_sched_barrier(0);
+    g[0] = Real((45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) * i60dx);
+    g[1] = Real((45.0 * (q1 - n1) - 9.0 * (q2 - n2) + (q3 - n3)) * i60dy);
+    g[2] = zc;
+  }
   __device__ __forceinline__ static double d2x(const double* a) {
     return -490.0 * a[0] + 270.0 * (a[1] + a[-1]) - 27.0 * (a[2] + a[-2]) +
            2.0 * (a[3] + a[-3]);
@@ -188,24 +200,25 @@ struct LdsSrc {
     return -490.0 * a[0] + 270.0 * (a[HW] + a[-HW]) - 27.0 * (a[2 * HW] + a[-2 * HW]) +
            2.0 * (a[3 * HW] + a[-3 * HW]);
   }
-  // gradient and Hessian of f; the seven x (y) values serve both D1 and D2
+  // gradient and Hessian of f; the seven x (y) values serve both D1 and D2.
+  // The reads are issued in two batches (the plane values and the z
+  // derivatives, then the mixed-derivative stencils), each waited for once.
   __device__ __forceinline__ void gh(int f, Real g[3], Real hh[6]) const {
     const double* a = P + f * HN + OWN;
-    {
-      const double c = a[0], p1 = a[1], m1 = a[-1], p2 = a[2], m2 = a[-2], p3 = a[3], m3 = a[-3];
-      g[0] = Real((45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) * i60dx);
-      hh[0] = Real((-490.0 * c + 270.0 * (p1 + m1) - 27.0 * (p2 + m2) + 2.0 * (p3 + m3)) *
-                   i180dx2);
-    }
-    {
-      const double c = a[0], q1 = a[HW], n1 = a[-HW], q2 = a[2 * HW], n2 = a[-2 * HW],
-                   q3 = a[3 * HW], n3 = a[-3 * HW];
-      g[1] = Real((45.0 * (q1 - n1) - 9.0 * (q2 - n2) + (q3 - n3)) * i60dy);
-      hh[1] = Real((-490.0 * c + 270.0 * (q1 + n1) - 27.0 * (q2 + n2) + 2.0 * (q3 + n3)) *
-                   i180dy2);
-    }
-    g[2] = Z[f * HN + OWN];
-    hh[2] = ZZ[f * NT];
+    const double c = a[0], p1 = a[1], m1 = a[-1], p2 = a[2], m2 = a[-2], p3 = a[3], m3 = a[-3];
+    const double q1 = a[HW], n1 = a[-HW], q2 = a[2 * HW], n2 = a[-2 * HW], q3 = a[3 * HW],
+                 n3 = a[-3 * HW];
+    const Real zc = Z[f * HN + OWN], zzc = ZZ[f * NT];
+    __builtin_amdgcn_sched_barrier(0);
+    g[0] = Real((45.0 * (p1 - m1) - 9.0 * (p2 - m2) + (p3 - m3)) * i60dx);
+    hh[0] = Real((-490.0 * c + 270.0 * (p1 + m1) - 27.0 * (p2 + m2) + 2.0 * (p3 + m3)) *
+                 i180dx2);
+    g[1] = Real((45.0 * (q1 - n1) - 9.0 * (q2 - n2) + (q3 - n3)) * i60dy);
+    hh[1] = Real((-490.0 * c + 270.0 * (q1 + n1) - 27.0 * (q2 + n2) + 2.0 * (q3 + n3)) *
+                 i180dy2);
+    g[2] = zc;
+    hh[2] = zzc;
+    __builtin_amdgcn_sched_barrier(0);
     hh[3] = q_h(f, 3) >= 0 && dx_slot(f) >= 0
                 ? Real(d1s(Dx + dx_slot(f) * DXP + DOWN, TX) * ixy)
                 : Real(0);
