@@ -221,11 +221,13 @@ def driver_bench(w, dt, ms_per_step, reps=5):
             "finite": finite}
 
 
-def split_error(w, nsteps):
+def split_error(w, nsteps, drivers):
     """Per-field error of the FP32-split form against plain FP64 after nsteps
-    steps from the same state with the same dt (both on the GPU): max |diff|
-    over the interior and the u_x, u_y ghost rows, divided by the max norm of
-    the physical field (A and u as vectors, ln rho, ln T) of the FP64 run."""
+    steps from the same state with the same dt, the driver target re-seeded
+    every 10 steps as in the timed runs (both on the GPU): max |diff| over
+    the interior and the u_x, u_y ghost rows, divided by the max norm of the
+    physical field (A and u as vectors, ln rho, ln T) of the FP64 run, and by
+    the component's own max norm."""
     import torch
     from paper_1908_08557_amd import cmhd
     outs = {}
@@ -236,7 +238,9 @@ def split_error(w, nsteps):
         if dt is None:
             dt = s.cfl_dt(st)
         t = 0.0
-        for _ in range(nsteps):
+        for i in range(nsteps):
+            if i % 10 == 0:
+                s.set_driver(drivers[(i // 10) % len(drivers)])
             t, _ = s.rk3_step(st, t, dt)
         torch.cuda.synchronize()
         outs[prec] = st
@@ -251,35 +255,99 @@ def split_error(w, nsteps):
             v = torch.cat([x[f, :3].reshape(-1), v])
         return v
 
-    err = {}
+    err, own = {}, {}
     for f in range(8):
-        scale = max(float(vals(a, q).abs().max()) for q in groups[f])
-        err[names[f]] = float((vals(b, f) - vals(a, f)).abs().max()) / scale
+        diff = float((vals(b, f) - vals(a, f)).abs().max())
+        err[names[f]] = diff / max(float(vals(a, q).abs().max()) for q in groups[f])
+        own[names[f]] = diff / float(vals(a, f).abs().max())
     del outs, a, b
     torch.cuda.empty_cache()
-    return err
+    return err, own
 
 
-def cpu_baseline():
-    """The oracle as it stands, on a bounded sample: a 128 x 128 x 64 box with
-    the 512^2 x 256 box's grid spacing and physics, eight RK3 steps (about
-    10 s of single-thread numpy work)."""
+ORACLE_JOBS = {
+    # name: (description, steps)
+    "C1": ("periodic 16^3, 10 RK3 steps (the small parity case, in full)", 10),
+    "C2": ("stratified 64^3 over 50 Mm, full physics, 100 RK3 steps (in full)", 100),
+    "strat512-sample": ("128x128x64 box with the 512x512x256 box's grid spacing and physics, "
+                        "2 RK3 steps", 2),
+}
+
+
+def _oracle_job(name):
+    """One oracle run in a child process (numpy float64, one thread)."""
     from oracle import mhd as O
     from paper_1908_08557_amd import workloads as W
-    nx, nz = 128, 64
-    dz = 50.0 / 255.0
-    w = W.stratified_box(nx, nx, nz, 50.0 * nx / 512, dz * (nz - 1), 2, 2, 3, "strat512-sample")
+    desc, nsteps = ORACLE_JOBS[name]
+    if name == "C1":
+        w = W.periodic_box(16)
+    elif name == "C2":
+        w = W.strat64()
+    else:
+        nx, nz = 128, 64
+        dz = 50.0 / 255.0
+        w = W.stratified_box(nx, nx, nz, 50.0 * nx / 512, dz * (nz - 1), 2, 2, 3,
+                             "strat512-sample")
+    g = w.grid
     F = O.from_compact(w.state)
-    O.fill_ghosts(F, w.grid, w.params, w.lnrho0_z)
-    dt = O.cfl_dt(F, w.grid, w.params)
-    drv = dict(uh=w.uh_target, ah=w.ah_target)
-    nsteps = 8
+    O.fill_ghosts(F, g, w.params, w.lnrho0_z)
+    dt = O.cfl_dt(F, g, w.params)
+    drv = dict(uh=w.uh_target, ah=w.ah_target) if g["zbc"] == "solar" else None
     t0 = time.perf_counter()
-    O.run(F, 0.0, dt, nsteps, w.grid, w.params, w.lnrho0_z, drv)
+    O.run(F, 0.0, dt, nsteps, g, w.params, w.lnrho0_z, drv)
     el = time.perf_counter() - t0
-    return dict(value=nx * nx * nz * nsteps / el, unit="zone-updates/s", cores=1, kind="oracle",
-                sample=f"{nx}x{nx}x{nz} box with the 512x512x256 spacing and physics, "
-                       f"{nsteps} RK3 steps, numpy float64 (single thread), {el:.1f} s")
+    zones = g["nx"] * g["ny"] * g["nz"]
+    return dict(workload=desc, steps=nsteps, seconds=el, value=zones * nsteps / el,
+                unit="zone-updates/s")
+
+
+def cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def start_cpu_baseline():
+    """The oracle as it stands on the host cores, started in child processes
+    (one thread each, in parallel with the GPU timing): the two small cases in
+    full and a bounded sample of the 512^2 x 256 workload."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    ex = ProcessPoolExecutor(max_workers=len(ORACLE_JOBS), mp_context=mp.get_context("spawn"))
+    futs = {name: ex.submit(_oracle_job, name) for name in ORACLE_JOBS}
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    return ex, futs
+
+
+def finish_cpu_baseline(ex, futs):
+    res = {name: f.result() for name, f in futs.items()}
+    ex.shutdown()
+    smp = res["strat512-sample"]
+    return dict(value=smp["value"], unit="zone-updates/s", cores=1, kind="oracle",
+                sample=f"{smp['workload']}, numpy float64 on one thread, "
+                       f"{smp['seconds']:.1f} s",
+                threads_per_run=1, parallel_runs=len(res), nproc=os.cpu_count(),
+                cpu_model=cpu_model(),
+                runs=res)
 
 
 def main():
@@ -297,6 +365,8 @@ def main():
                     help="skip the eager vs HIP-graph timing of the small boxes")
     ap.add_argument("--no-ar1024", action="store_true",
                     help="skip the 1024x1024x256 active-region box (FP32-split)")
+    ap.add_argument("--ar1024-steps", type=int, default=200,
+                    help="timed steps of the 1024x1024x256 box (its workload runs 200)")
     ap.add_argument("--split-error-steps", type=int, default=100,
                     help="steps of the FP32-split vs FP64 error run (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -322,6 +392,10 @@ def main():
         return
     from paper_1908_08557_amd import workloads as W
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle runs started in child processes")
+        cpu = start_cpu_baseline()
     log(f"[bench] building workload {args.workload}")
     w = W.WORKLOADS[args.workload]()
     g = w.grid
@@ -359,20 +433,25 @@ def main():
                                "of one substage)",
                      "kernel_ms_per_launch": r["substage_ms"],
                      "ghosts_ms": r["ghosts_ms"],
-                     "alg_bytes_per_launch": BYTES_PER_ZONE_STEP / 3.0 * g["nx"] * g["ny"] * g["nz"]},
+                     "alg_bytes_per_launch": BYTES_PER_ZONE_STEP / 3.0 * g["nx"] * g["ny"] * g["nz"],
+                     # the whole step (three substages and their boundary
+                     # work) against the same 640 B per zone
+                     "step_GBs": r["step_GBs"], "step_frac": r["step_GBs"] / HBM_PEAK_GBS},
     }
     if "fp32_split" in res and main_prec == "fp64":
         s = res["fp32_split"]
         out["fp32_split"] = {"value": s["value"], "ms_per_step": s["ms_per_step"],
                              "speedup_vs_fp64": s["value"] / r["value"],
                              "roofline_frac": s["frac"],
+                             "step_frac": s["step_GBs"] / HBM_PEAK_GBS,
                              "substage_ms": s["substage_ms"],
                              "ghosts_ms": s["ghosts_ms"]}
         if args.split_error_steps > 0:
             log(f"[bench] fp32_split vs fp64 error after {args.split_error_steps} steps")
-            e = split_error(w, args.split_error_steps)
-            log(f"[bench] split error: {e}")
+            e, eo = split_error(w, args.split_error_steps, drivers)
+            log(f"[bench] split error: {e} (own maxima {eo})")
             out["fp32_split"]["rel_err_vs_fp64"] = e
+            out["fp32_split"]["rel_err_vs_fp64_own_max"] = eo
             out["fp32_split"]["rel_err_steps"] = args.split_error_steps
     # the HBM rate a plain device copy reaches on this GPU (read + write), the
     # practical ceiling beside the published peak
@@ -398,20 +477,23 @@ def main():
                                           "0.8 Mm (top 141 Mm)",
                               "value": rs["value"], "ms_per_step": rs["ms_per_step"],
                               "substage_ms": rs["substage_ms"], "roofline_frac": rs["frac"],
+                              "step_frac": rs["step_GBs"] / HBM_PEAK_GBS,
                               "steps": max(args.steps // 2, 1), "finite": rs["finite"]}
     if not args.no_ar1024 and w.name == "strat512":
         # the active-region box of the same physics, 1024 x 1024 x 256 over
         # 64 Mm with 32 bipoles, in the FP32-split form
         log("[bench] ar1024 fp32_split")
         wa = W.ar1024()
-        ra = run_gpu(wa, "fp32_split", max(args.steps // 2, 1), args.warmup,
+        ra = run_gpu(wa, "fp32_split", args.ar1024_steps, args.warmup,
                      [torch.as_tensor(W.driver_reseed(wa, 100 + k), device="cuda")
-                      for k in range(2)])
+                      for k in range(4)])
         log(f"[bench] ar1024: {ra}")
-        out["ar1024"] = {"workload": "ar1024: 1024x1024x256 over 64 Mm, 32 bipoles, FP32-split",
+        out["ar1024"] = {"workload": "ar1024: 1024x1024x256 over 64 Mm, 32 bipoles, FP32-split, "
+                                     "driver re-seeded every 10 steps",
                          "value": ra["value"], "ms_per_step": ra["ms_per_step"],
                          "substage_ms": ra["substage_ms"], "roofline_frac": ra["frac"],
-                         "steps": max(args.steps // 2, 1), "finite": ra["finite"]}
+                         "step_frac": ra["step_GBs"] / HBM_PEAK_GBS,
+                         "steps": args.ar1024_steps, "finite": ra["finite"]}
         del wa
     if not args.no_graph:
         log("[bench] small boxes, eager vs HIP graph")
@@ -421,9 +503,10 @@ def main():
         log("[bench] granulation driver")
         out["driver"] = driver_bench(w, r["dt"], r["ms_per_step"])
         log(f"[bench] driver: {out['driver']}")
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle on a sample)")
-        out["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        log("[bench] cpu baseline: waiting for the oracle runs")
+        out["cpu_baseline"] = finish_cpu_baseline(*cpu)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 

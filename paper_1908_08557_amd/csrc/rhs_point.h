@@ -202,17 +202,41 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   m.ohm = ohm;
 }
 
-// rho and T (float path: from the float64 state, since ln rho ~ 20 and
-// ln T ~ 14 carry too few bits in float)
+// The pointwise thermodynamic values the parts of the right-hand side share,
+// formed once per zone: T, 1/rho and 1/(c_v T) (float path: from the float64
+// state, since ln rho ~ 20 and ln T ~ 14 carry too few bits in float).
+template <typename S>
+struct PointVals {
+  S T, irho, icvT;
+};
+
+// T and 1/(c_v T); 1/rho (the two halves of point_vals, which a kernel may
+// form on different waves)
 template <typename S, class Src>
-__device__ __forceinline__ void rho_T(const Src& src, S& rho, S& T) {
+__device__ __forceinline__ void point_temperature(const Src& src, const KParams& p, S& T,
+                                                  S& icvT) {
   if constexpr (std::is_same<S, float>::value) {
-    rho = float(exp(src.v64(LR)));
-    T = float(exp(src.v64(LT)));
+    const double T64 = exp(src.v64(LT));
+    T = float(T64);
+    icvT = float(p.inv_cv / T64);
   } else {
-    rho = s_exp(src.v(LR));
     T = s_exp(src.v(LT));
+    icvT = S(p.inv_cv) / T;
   }
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ S point_irho(const Src& src) {
+  if constexpr (std::is_same<S, float>::value) return float(exp(-src.v64(LR)));
+  else return s_exp(-src.v(LR));
+}
+
+template <typename S, class Src>
+__device__ __forceinline__ PointVals<S> point_vals(const Src& src, const KParams& p) {
+  PointVals<S> pv;
+  point_temperature<S>(src, p, pv.T, pv.icvT);
+  pv.irho = point_irho<S>(src);
+  return pv;
 }
 
 // The terms of the fluid equations that need the magnetic part or the
@@ -223,22 +247,19 @@ __device__ __forceinline__ void rho_T(const Src& src, S& rho, S& T) {
 //   Q_cond / (rho c_v T) = (kappa0 T^5/2 / (rho c_v))
 //       [7/2 (b.G)^2 + b b:H + (b_i d_i B_j G_j - 2 (b.G) b_i b_k d_i B_k) / |B|_r]
 // (the float path forms the coefficient kappa0 T^5/2 / (rho c_v) in float64).
-template <typename S, class Src>
-__device__ __forceinline__ void rhs_lorentz(const Src& src, const MagState<S>& m, S add[3]) {
-  S rho, T;
-  rho_T(src, rho, T);
-  const S irho = S(1.0) / rho;
+template <typename S>
+__device__ __forceinline__ void rhs_lorentz(const MagState<S>& m, const PointVals<S>& pv,
+                                            S add[3]) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) add[i] = m.JxB[i] * irho;
+  for (int i = 0; i < 3; ++i) add[i] = m.JxB[i] * pv.irho;
 }
 
 template <typename S, class Src>
 __device__ __forceinline__ S rhs_heating(const Src& src, const PointCtx<S>& pc,
-                                         const KParams& p, const MagState<S>& m) {
+                                         const KParams& p, const MagState<S>& m,
+                                         const PointVals<S>& pv) {
   constexpr bool kFloat = std::is_same<S, float>::value;
-  S rho, T;
-  rho_T(src, rho, T);
-  S e = m.ohm / (rho * S(p.cv) * T);
+  S e = m.ohm * pv.irho * pv.icvT;
   const bool swamp_T = p.chi_s != 0.0 && pc.w != 0.0;
   if (p.kappa0 != 0.0 || swamp_T) {
     S G[3], H[6];
@@ -267,9 +288,9 @@ __device__ __forceinline__ S rhs_heating(const Src& src, const PointCtx<S>& pc,
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_mag_to_fluid(const Src& src, const PointCtx<S>& pc,
                                                  const KParams& p, const MagState<S>& m,
-                                                 S add[4]) {
-  rhs_lorentz<S>(src, m, add);
-  add[3] = rhs_heating<S>(src, pc, p, m);
+                                                 const PointVals<S>& pv, S add[4]) {
+  rhs_lorentz<S>(m, pv, add);
+  add[3] = rhs_heating<S>(src, pc, p, m, pv);
 }
 
 // optically thin loss Q_rad/(rho c_v T) = exp(ln rho + lnL(ln T) - ln T) W(ln T) / c_v
@@ -368,8 +389,9 @@ __device__ __forceinline__ S rhs_newton(const Src& src, const KParams& p, const 
 //   S:S = 1/2 sum_ij a_ij^2 + 1/2 sum_ij a_ij a_ji - (div u)^2 / 3,
 // and grad div u takes the c-th Hessian column of u_c.
 template <typename S, class Src>
-__device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S out[NF],
-                                             S& divu_out, S& SS_out) {
+__device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p,
+                                             const PointVals<S>& pv, S out[NF], S& divu_out,
+                                             S& SS_out) {
   const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   S Glr[3], GlT[3];
   src.grad(LR, Glr);
@@ -377,10 +399,7 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S
   S mom[3], divu = S(0.0), sq = S(0.0), cross = S(0.0);
   S a01 = S(0.0), a02 = S(0.0), a12 = S(0.0);   // a_01, a_02, a_12 for the cross sum
   {
-    S T;
-    if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
-    else T = s_exp(src.v(LT));
-    const S RT = S(p.R) * T;
+    const S RT = S(p.R) * pv.T;
 #pragma unroll
     for (int i = 0; i < 3; ++i) mom[i] = -RT * (Glr[i] + GlT[i]);
   }
@@ -435,12 +454,10 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p, S
 //            (+ Newtonian cooling)
 // with div u and S:S from rhs_momentum.  In two pieces: rhs_scalars_pre needs
 // no velocity gradient (LRp, LTp the two equations without their div u and
-// S:S terms, cS = 2 nu / (c_v T) the factor of S:S), rhs_scalars_post adds
-// those terms.
+// S:S terms), rhs_scalars_post adds those terms.
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_scalars_pre(const Src& src, const PointCtx<S>& pc,
-                                                const KParams& p, S nc, S& LRp, S& LTp,
-                                                S& cS) {
+                                                const KParams& p, S nc, S& LRp, S& LTp) {
   const S u[3] = {src.v(UX), src.v(UY), src.v(UZ)};
   {
     S Glr[3];
@@ -450,40 +467,38 @@ __device__ __forceinline__ void rhs_scalars_pre(const Src& src, const PointCtx<S
     LRp = (S(p.D_rho) + S(p.chi_rho) * S(pc.w)) * src.lapr() - udr + S(p.D_rho) * gr2;
   }
   {
-    S T;
-    if constexpr (std::is_same<S, float>::value) T = float(exp(src.v64(LT)));
-    else T = s_exp(src.v(LT));
     S GlT[3];
     src.grad(LT, GlT);
     const S udT = u[0] * GlT[0] + u[1] * GlT[1] + u[2] * GlT[2];
     LTp = nc - udT;
-    cS = S(2.0) * S(p.nu) / (S(p.cv) * T);
   }
 }
 
+// 2 nu S:S / (c_v T) = (2 nu / (c_v T)) S:S
 template <typename S>
-__device__ __forceinline__ void rhs_scalars_post(const KParams& p, S LRp, S LTp, S cS, S divu,
-                                                 S SS, S rad, S& dlr, S& dlT) {
+__device__ __forceinline__ void rhs_scalars_post(const KParams& p, const PointVals<S>& pv, S LRp,
+                                                 S LTp, S divu, S SS, S rad, S& dlr, S& dlT) {
   dlr = LRp - divu;
-  dlT = cS * SS + LTp - rad - S(p.gm1) * divu;
+  dlT = S(2.0 * p.nu) * pv.icvT * SS + LTp - rad - S(p.gm1) * divu;
 }
 
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_scalars(const Src& src, const PointCtx<S>& pc,
-                                            const KParams& p, S divu, S SS, S rad, S nc,
-                                            S out[NF]) {
-  S LRp, LTp, cS;
-  rhs_scalars_pre<S>(src, pc, p, nc, LRp, LTp, cS);
-  rhs_scalars_post<S>(p, LRp, LTp, cS, divu, SS, rad, out[LR], out[LT]);
+                                            const KParams& p, const PointVals<S>& pv, S divu,
+                                            S SS, S rad, S nc, S out[NF]) {
+  S LRp, LTp;
+  rhs_scalars_pre<S>(src, pc, p, nc, LRp, LTp);
+  rhs_scalars_post<S>(p, pv, LRp, LTp, divu, SS, rad, out[LR], out[LT]);
 }
 
 // the fluid equations without the magnetic terms: momentum, continuity, energy
 template <typename S, class Src>
 __device__ __forceinline__ void rhs_fluid_core(const Src& src, const PointCtx<S>& pc,
-                                               const KParams& p, S rad, S nc, S out[NF]) {
+                                               const KParams& p, const PointVals<S>& pv, S rad,
+                                               S nc, S out[NF]) {
   S divu, SS;
-  rhs_momentum<S>(src, p, out, divu, SS);
-  rhs_scalars<S>(src, pc, p, divu, SS, rad, nc, out);
+  rhs_momentum<S>(src, p, pv, out, divu, SS);
+  rhs_scalars<S>(src, pc, p, pv, divu, SS, rad, nc, out);
 }
 
 // the magnetic part's contributions added to the fluid equations
@@ -526,10 +541,11 @@ __device__ __forceinline__ void rhs_eval(const Src& src, const PointCtx<S>& pc,
   S add[4];
   const S rad = rhs_radiation<S>(src, p, ParamRadTable{p});
   const S nc = rhs_newton<S>(src, p, ParamNcTable{p}, pc);
+  const PointVals<S> pv = point_vals<S>(src, p);
   rhs_magnetic<S>(src, pc, p, out, m);
-  rhs_mag_to_fluid<S>(src, pc, p, m, add);
+  rhs_mag_to_fluid<S>(src, pc, p, m, pv, add);
   CMHD_FENCE();
-  rhs_fluid_core<S>(src, pc, p, rad, nc, out);
+  rhs_fluid_core<S>(src, pc, p, pv, rad, nc, out);
   rhs_add_magnetic<S>(add, out);
   rhs_boundary_magnetic<S>(src, pc, p, out);
   rhs_boundary_fluid<S>(src, pc, p, out);

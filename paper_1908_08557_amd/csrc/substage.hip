@@ -19,8 +19,9 @@
 //      waves, which then load the next plane into their ring, the others
 //      by the right-hand-side waves, which also copy the RK register and f
 //      of the own tile into LDS and form the pointwise terms: the radiative
-//      loss (magnetic waves), the parts of continuity and energy without
-//      div u and S:S and the Newtonian cooling (fluid).
+//      loss and 1/rho (magnetic waves), the parts of continuity and energy
+//      without div u and S:S, the Newtonian cooling, T and 1/(c_v T)
+//      (fluid).
 //   R  right-hand side at the own columns, every derivative read from LDS
 //      on demand: the magnetic waves the induction equation, B, J, Spitzer
 //      conduction, Ohmic heating, the swamp diffusion of ln T and the Lorentz
@@ -68,8 +69,8 @@ struct Smem {
   Real ZZ[NF][NT];          // d2/dz2 at the own columns
   double Dx[NDX][DXP];      // unscaled D1_x
   Real X[NXCH][NT];         // magnetic -> fluid
-  Real Q[7][NT];            // momentum RHS (3), d ln rho/dt, d ln T/dt (partial), radiative loss,
-                            // 2 nu/(c_v T)
+  Real Q[9][NT];            // momentum RHS (3), d ln rho/dt, d ln T/dt (partial), radiative loss,
+                            // T, 1/(c_v T), 1/rho
   Real QA[3][NT];           // induction RHS
   double R[NF][NT];         // the RK register of the own columns (global->LDS copies)
   double Fown[NF][NT];      // f at the own columns (global->LDS copies)
@@ -538,6 +539,7 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
                              &sm.Dx[0][0], p.i60dx, p.i60dy, p.i180dx2, p.i180dy2, 0.0};
       if (mag) {
         sm.Q[5][oo] = rhs_radiation<Real>(src, p, LdsRadTable{sm.rad});
+        sm.Q[8][oo] = point_irho<Real>(src);
       } else {
         PointCtx<Real> pc;
         swamp(p, k, pc.w, pc.dw);
@@ -547,11 +549,13 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
           pc.nc_lnT0 = p.nc_tab[p.nc_n + k + NG];
           nc = rhs_newton<Real>(src, p, ParamNcTable{p}, pc);
         }
-        Real LRp, LTp, cS;
-        rhs_scalars_pre<Real>(src, pc, p, nc, LRp, LTp, cS);
+        Real LRp, LTp, T, icvT;
+        rhs_scalars_pre<Real>(src, pc, p, nc, LRp, LTp);
+        point_temperature<Real>(src, p, T, icvT);
         sm.Q[3][oo] = LRp;
         sm.Q[4][oo] = LTp;
-        sm.Q[6][oo] = cS;
+        sm.Q[6][oo] = T;
+        sm.Q[7][oo] = icvT;
       }
     }
     copies_barrier();  // B2: D1_x and the pointwise terms staged, the copies landed
@@ -569,21 +573,23 @@ __global__ __launch_bounds__(NTB) void k_substage(const double* __restrict__ f,
       rhs_magnetic<Real>(src, pc, p, out, m);
 #pragma unroll
       for (int i = 0; i < 3; ++i) sm.QA[i][oo] = out[AX + i];
+      const PointVals<Real> pv{sm.Q[6][oo], sm.Q[8][oo], sm.Q[7][oo]};
       {
         Real add[3];
-        rhs_lorentz<Real>(src, m, add);
+        rhs_lorentz<Real>(m, pv, add);
 #pragma unroll
         for (int i = 0; i < 3; ++i) sm.X[i][oo] = add[i];
       }
-      sm.X[3][oo] = rhs_heating<Real>(src, pc, p, m);
+      sm.X[3][oo] = rhs_heating<Real>(src, pc, p, m, pv);
     } else {
       Real out[NF], divu, SS;
-      rhs_momentum<Real>(src, p, out, divu, SS);
+      const PointVals<Real> pv{sm.Q[6][oo], Real(0.0), sm.Q[7][oo]};
+      rhs_momentum<Real>(src, p, pv, out, divu, SS);
 #pragma unroll
       for (int i = 0; i < 3; ++i) sm.Q[i][oo] = out[UX + i];
       Real dlr, dlT;
-      rhs_scalars_post<Real>(p, sm.Q[3][oo], sm.Q[4][oo], sm.Q[6][oo], divu, SS, sm.Q[5][oo],
-                             dlr, dlT);
+      rhs_scalars_post<Real>(p, pv, sm.Q[3][oo], sm.Q[4][oo], divu, SS, sm.Q[5][oo], dlr,
+                             dlT);
       sm.Q[3][oo] = dlr;
       sm.Q[4][oo] = dlT;
     }
