@@ -15,8 +15,8 @@
 //      grid).
 //      Meanwhile the right-hand-side waves finish plane k-1 (F below).
 //   X  D1_x of the six fields with an xy mixed derivative (A, u_x, u_y,
-//      ln T) on the tile columns and all 22 rows, those of A by the window
-//      waves, which then load the next plane into their ring, the others
+//      ln T) on the tile columns and all 22 rows, those of A_x, A_y by the
+//      window waves, which then load the next plane into their ring, the others
 //      by the right-hand-side waves, which also copy the RK register and f
 //      of the own tile into LDS and form the pointwise terms: the radiative
 //      loss and 1/rho (magnetic waves), the parts of continuity and energy
@@ -301,17 +301,19 @@ __device__ __forceinline__ void zmetric(const KParams& p, int k, double& c1, dou
 // D1_x (unscaled) of the xy-mixed fields on the tile columns and all 22 rows
 // of the staged plane (the right-hand side reads it for the xy mixed
 // derivatives), between the first and second barrier: the window waves form
-// the slots [0, NDX/2) with at most two values in flight (they hold their z
+// the slots [0, NDXW) with at most two values in flight (they hold their z
 // window meanwhile), the right-hand-side waves the rest.  t is the thread's
 // index within its group of 512.
-constexpr int NDXH = NDX / 2 * DXP;   // items per group
+constexpr int NDXW = 2;   // slots of the window waves
 template <typename Real, bool NEWTON, bool WINDOW>
 __device__ __forceinline__ void stencils_dx(Smem<Real, NEWTON>& sm, int t) {
+  constexpr int s0 = WINDOW ? 0 : NDXW;
+  constexpr int n = (WINDOW ? NDXW : NDX - NDXW) * DXP;
   // (opaque: the per-item indices are re-derived at every plane, not held
   // in registers across the plane loop)
 #pragma unroll 1
-  for (int i = opaque(t); i < NDXH; i += NT2) {
-    const int s = i / DXP + (WINDOW ? 0 : NDX / 2), pt = i - (i / DXP) * DXP;
+  for (int i = opaque(t); i < n; i += NT2) {
+    const int s = i / DXP + s0, pt = i - (i / DXP) * DXP;
     const int row = pt / TX, col = pt - row * TX;
     const double* a = &sm.P[dx_field(s)][row * HW + col + NG];
     sm.Dx[s][pt] = WINDOW ? d1s_lean(a, 1) : d1s(a, 1);
