@@ -270,7 +270,7 @@ ORACLE_JOBS = {
     "C1": ("periodic 16^3, 10 RK3 steps (the small parity case, in full)", 10),
     "C2": ("stratified 64^3 over 50 Mm, full physics, 100 RK3 steps (in full)", 100),
     "strat512-sample": ("128x128x64 box with the 512x512x256 box's grid spacing and physics, "
-                        "2 RK3 steps", 2),
+                        "8 RK3 steps", 8),
 }
 
 
