@@ -463,7 +463,7 @@ def main():
         out["roofline"]["traffic"] = tr["hbm_bytes_per_substage"]
         out["roofline"]["traffic_GBs"] = tr["hbm_bytes_per_substage"] / (r["substage_ms"] * 1e-3) / 1e9
         out["roofline"]["traffic_source"] = tr["profile"]
-        out["roofline"]["valu_busy_pct"] = tr["valu_busy_pct_fused"]
+        out["roofline"]["valu_busy_pct"] = tr["valu_busy_pct"]
     out["finite"] = all(v["finite"] for v in res.values())
     if not args.no_stretched and w.name == "strat512":
         # the same box on the paper's kind of z grid (100 km -> 800 km), FP64
