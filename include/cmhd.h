@@ -210,10 +210,9 @@ cmhd_status cmhd_fill_ghosts(cmhd_ctx* ctx, double* state, double t);
  * (if non-NULL) holds it.  The derived ghosts of the state are refreshed on
  * entry and are stale on return; the interior and the ux, uy lower ghost
  * planes hold the new state.  Needs a bound workspace (ESTATE).
- * With dt > 0 the call only launches kernels and records and waits on events
- * (on the context stream and a second stream of the context, joined back
- * before it returns): no allocation, copy, memset or host synchronisation, so
- * it may be captured into a HIP graph.  The switch-on ramp and the snapshot
+ * With dt > 0 the call only launches kernels on the context stream (and,
+ * while profiling is enabled, records events there): no allocation, copy,
+ * memset or host synchronisation, so it may be captured into a HIP graph.  The switch-on ramp and the snapshot
  * weight are evaluated on the host from *t at the call and are fixed in a
  * captured graph. */
 cmhd_status cmhd_rk3_step(cmhd_ctx* ctx, double* state, double* t, double dt,

@@ -1,5 +1,5 @@
 """GPU parity at the benchmark's full size, in the launch configuration that
-bench.py times (512 x 512 x 256, pipelined substage, XCD-ordered tiles), and
+bench.py times (512 x 512 x 256, two z chunks of 128 planes, XCD-ordered tiles), and
 on the largest box (1024 x 1024 x 256), on sampled outputs: one step of the whole box on the GPU, and for each sampled
 zone the oracle run on a 25^3 patch around it.  After one RK3 step a zone
 depends on the state within 9 zones (three substages of the 3-zone stencils),

@@ -1,7 +1,7 @@
 """HIP-graph capture of the forward step.  With dt given, the switch-on ramp
 finished (or off) and a single driver target, cmhd_rk3_step issues only
-kernel launches and event records/waits on the context stream and its own
-second stream (no allocation, copy, memset or host synchronisation), so a
+kernel launches on the context stream (no allocation, copy, memset, event
+or host synchronisation), so a
 caller can capture several steps into one graph and replay them.  The
 time-dependent host scalars of a step (the ramp, the snapshot weight) are
 fixed at capture, which is why the ramp is off here.  Every replay, with
@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("shape", [(32, 32, 24), (256, 256, 32)])
 def test_graph_replays_equal_eager_steps(shape):
-    # 32^2 x 24: one launch per kernel; 256^2 x 32: the pipelined substage,
-    # whose z-derivative chunks run on the library's second stream
+    # 32^2 x 24: small z chunks; 256^2 x 32: 256 tiles in 8 z chunks of 4
+    # planes each
     import torch
     from paper_1908_08557_amd import cmhd
     nx, ny, nz = shape

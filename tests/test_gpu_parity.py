@@ -158,12 +158,12 @@ def test_newton_cooling_dt_limit():
     assert dt <= w.params["c_nudge"] / 5e4 * (1 + 1e-12)
 
 
-_PIPELINED = {}   # oracle result shared by the two precisions
+_ZCHUNKED = {}   # oracle result shared by the two precisions
 
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_split"])
-def test_pipelined_substage(precision):
+def test_z_chunked_substage(precision):
     # 256 x 256 x 32 (256 tiles, 8 z chunks of 4 planes: each block's z
     # window starts and ends inside the box).  FP64 against the oracle after
     # two steps; the FP32-split form against the same oracle at its own
@@ -171,24 +171,24 @@ def test_pipelined_substage(precision):
     import torch
     from paper_1908_08557_amd import cmhd
     w = W.small_stratified(256, 256, 32, Lxy=80.0, z1=20.0, nbip=4)
-    print(f"[case] pipelined substage 256x256x32 {precision}", flush=True)
-    if "ref" not in _PIPELINED:
-        _PIPELINED["dt"] = oracle_dt(w)
-        _PIPELINED["ref"] = oracle_run(w, 2, _PIPELINED["dt"])
-        _PIPELINED["floor"] = oracle_floor(w, 2, _PIPELINED["dt"], _PIPELINED["ref"])
-    dt = _PIPELINED["dt"]
+    print(f"[case] z-chunked substage 256x256x32 {precision}", flush=True)
+    if "ref" not in _ZCHUNKED:
+        _ZCHUNKED["dt"] = oracle_dt(w)
+        _ZCHUNKED["ref"] = oracle_run(w, 2, _ZCHUNKED["dt"])
+        _ZCHUNKED["floor"] = oracle_floor(w, 2, _ZCHUNKED["dt"], _ZCHUNKED["ref"])
+    dt = _ZCHUNKED["dt"]
     s = cmhd.solver_for(w, precision)
     st = s.new_state(w.state)
     t = 0.0
     for _ in range(2):
         t, _ = s.rk3_step(st, t, dt)
     got = st.cpu().numpy()
-    ref = _PIPELINED["ref"]
+    ref = _ZCHUNKED["ref"]
     if precision == "fp64":
-        assert_parity(got, ref, True, 1e-12, "pipelined 256x256x32 fp64",
-                      floor=_PIPELINED["floor"])
+        assert_parity(got, ref, True, 1e-12, "z-chunked 256x256x32 fp64",
+                      floor=_ZCHUNKED["floor"])
     else:
-        assert_parity(got, ref, True, 2e-6, "pipelined 256x256x32 fp32_split",
+        assert_parity(got, ref, True, 2e-6, "z-chunked 256x256x32 fp32_split",
                       field_norm=SPLIT_SHORT_BY_FIELD)
 
 

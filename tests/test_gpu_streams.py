@@ -1,6 +1,6 @@
 """The context follows the caller's stream: steps issued on a side stream
-(the pipelined substage forks the library's second stream from it and joins
-back) equal the steps on the default stream bitwise; and the kernel-timing
+(every kernel of the step is launched on the context's stream) equal the
+steps on the default stream bitwise; and the kernel-timing
 API (cmhd_profile_enable / cmhd_profile_read) counts the substages, resets on
 read and rejects an unknown selector."""
 import ctypes

@@ -97,12 +97,12 @@ def test_stretched_time_step_and_bz_plane():
 
 
 @pytest.mark.timeout(600)
-def test_stretched_pipelined_substage():
+def test_stretched_z_chunked_substage():
     # 256 x 256 x 32 on a stretched grid: 8 z chunks of 4 planes, the z
     # window with the metric of each plane
     w = W.small_stretched(256, 256, 32, Lxy=80.0, nbip=4)
-    print("[case] stretched pipelined 256x256x32", flush=True)
+    print("[case] stretched z-chunked 256x256x32", flush=True)
     dt = oracle_dt(w)
     ref = oracle_run(w, 1, dt)
-    assert_parity(_gpu_run(w, 1, dt), ref, True, 1e-12, "stretched pipelined 1 step",
+    assert_parity(_gpu_run(w, 1, dt), ref, True, 1e-12, "stretched z-chunked 1 step",
                   floor=oracle_floor(w, 1, dt, ref))
