@@ -6,7 +6,8 @@ depends on the state within 9 zones (three substages of the 3-zone stencils),
 so a patch that reaches 12 zones out, with periodic wrap at its edges, gives
 the oracle's value of its centre exactly (up to rounding); samples stay 12
 zones away from the photosphere and below the swamp layer, where the solar
-boundary rules would enter."""
+boundary rules would enter (the boundary work at these plane sizes is checked
+whole in test_gpu_boundary_fullsize.py)."""
 import numpy as np
 import pytest
 
