@@ -319,35 +319,64 @@ def cpu_model():
     return "unknown"
 
 
-def start_cpu_baseline():
-    """The oracle as it stands on the host cores, started in child processes
-    (one thread each, in parallel with the GPU timing): the two small cases in
-    full and a bounded sample of the 512^2 x 256 workload."""
+def _spawn_pool(nworkers):
+    """A pool of fresh child processes (spawned, so that no GPU state is
+    inherited) whose numpy runs on one thread each."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    ex = ProcessPoolExecutor(max_workers=len(ORACLE_JOBS), mp_context=mp.get_context("spawn"))
-    futs = {name: ex.submit(_oracle_job, name) for name in ORACLE_JOBS}
+    ex = ProcessPoolExecutor(max_workers=nworkers, mp_context=mp.get_context("spawn"))
+    ex.submit(int, 0).result()   # start the workers now, with this environment
     for k, v in saved.items():
         if v is None:
             os.environ.pop(k, None)
         else:
             os.environ[k] = v
+    return ex
+
+
+def start_cpu_baseline():
+    """The oracle as it stands on the host cores, started in child processes
+    (one thread each, in parallel with the GPU timing): the two small cases in
+    full and a bounded sample of the 512^2 x 256 workload."""
+    ex = _spawn_pool(len(ORACLE_JOBS))
+    futs = {name: ex.submit(_oracle_job, name) for name in ORACLE_JOBS}
     return ex, futs
 
 
-def finish_cpu_baseline(ex, futs):
+def all_cores_run(name, ncores):
+    """ncores independent copies of one oracle run at once, one per core (the
+    oracle is single-threaded numpy): the host's aggregate rate."""
+    ex = _spawn_pool(ncores)
+    for _ in ex.map(int, range(ncores)):   # every worker started before the clock
+        pass
+    t0 = time.perf_counter()
+    res = list(ex.map(_oracle_job, [name] * ncores))
+    el = time.perf_counter() - t0
+    ex.shutdown()
+    desc, nsteps = ORACLE_JOBS[name]
+    zu = sum(r["value"] * r["seconds"] for r in res)   # zone-updates done in all
+    return dict(workload=desc, copies=ncores, seconds=el, value=zu / el,
+                unit="zone-updates/s")
+
+
+def finish_cpu_baseline(ex, futs, all_cores=True):
     res = {name: f.result() for name, f in futs.items()}
     ex.shutdown()
     smp = res["strat512-sample"]
-    return dict(value=smp["value"], unit="zone-updates/s", cores=1, kind="oracle",
-                sample=f"{smp['workload']}, numpy float64 on one thread, "
-                       f"{smp['seconds']:.1f} s",
-                threads_per_run=1, parallel_runs=len(res), nproc=os.cpu_count(),
-                cpu_model=cpu_model(),
-                runs=res)
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = dict(value=smp["value"], unit="zone-updates/s", cores=1, kind="oracle",
+               sample=f"{smp['workload']}, numpy float64 on one thread, "
+                      f"{smp['seconds']:.1f} s",
+               threads_per_run=1, nproc=os.cpu_count(), cores_available=ncores,
+               cpu_model=cpu_model(), omp_num_threads_of_runs=1, one_thread=res)
+    if all_cores:
+        # after the GPU timing, so that the oracle copies do not slow the
+        # process that launches the GPU work
+        out["all_cores"] = {name: all_cores_run(name, ncores) for name in ORACLE_JOBS}
+    return out
 
 
 def main():
