@@ -227,7 +227,9 @@ def split_error(w, nsteps, drivers):
     every 10 steps as in the timed runs (both on the GPU): max |diff| over
     the interior and the u_x, u_y ghost rows, divided by the max norm of the
     physical field (A and u as vectors, ln rho, ln T) of the FP64 run, and by
-    the component's own max norm."""
+    the component's own max norm, except A_z: of a potential-field state it is
+    a cancellation residue, measured against |A| in both figures (its own
+    scale, max |A_z| / max |A|, is returned beside them)."""
     import torch
     from paper_1908_08557_amd import cmhd
     outs = {}
@@ -258,11 +260,13 @@ def split_error(w, nsteps, drivers):
     err, own = {}, {}
     for f in range(8):
         diff = float((vals(b, f) - vals(a, f)).abs().max())
-        err[names[f]] = diff / max(float(vals(a, q).abs().max()) for q in groups[f])
-        own[names[f]] = diff / float(vals(a, f).abs().max())
+        field = max(float(vals(a, q).abs().max()) for q in groups[f])
+        err[names[f]] = diff / field
+        own[names[f]] = diff / (field if names[f] == "Az" else float(vals(a, f).abs().max()))
+    az_scale = float(vals(a, 2).abs().max()) / max(float(vals(a, q).abs().max()) for q in range(3))
     del outs, a, b
     torch.cuda.empty_cache()
-    return err, own
+    return err, own, az_scale
 
 
 ORACLE_JOBS = {
@@ -477,10 +481,11 @@ def main():
                              "ghosts_ms": s["ghosts_ms"]}
         if args.split_error_steps > 0:
             log(f"[bench] fp32_split vs fp64 error after {args.split_error_steps} steps")
-            e, eo = split_error(w, args.split_error_steps, drivers)
+            e, eo, azs = split_error(w, args.split_error_steps, drivers)
             log(f"[bench] split error: {e} (own maxima {eo})")
             out["fp32_split"]["rel_err_vs_fp64"] = e
             out["fp32_split"]["rel_err_vs_fp64_own_max"] = eo
+            out["fp32_split"]["Az_residue_scale"] = azs
             out["fp32_split"]["rel_err_steps"] = args.split_error_steps
     # the HBM rate a plain device copy reaches on this GPU (read + write), the
     # practical ceiling beside the published peak

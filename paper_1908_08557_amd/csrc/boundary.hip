@@ -106,30 +106,28 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// transform b: elements at base(b) + j*stride, j = 0..n-1, where
-// base(b) = (b / inner) * outer + (b % inner) * istride.  One thread per
-// element (blockDim.x = n <= 1024), radix-2 decimation in time on the
-// bit-reversed input: thread t holds element t of the current stage.  A
-// butterfly's partner t ^ half lies in the same wavefront for half < 64 and
-// is exchanged with a lane shuffle; the longer stages exchange through LDS.
-// The twiddles exp(sign 2 pi i k / n), k < n/2, are evaluated once per block
-// into LDS (the stage of length len uses k = pos n / len).
-__global__ __launch_bounds__(1024) void k_fft1d(double2* __restrict__ data, int n, int logn,
-                                                long long stride, int inner, long long outer,
-                                                long long istride, double sign) {
-  __shared__ double2 buf[1024];
-  __shared__ double2 tw[512];
-  const long long b = blockIdx.x;
-  const long long base = (b / inner) * outer + (b % inner) * istride;
-  const int t = threadIdx.x;
-  const int r = (int)(__brev((unsigned)t) >> (32 - logn));
-  double2 v = data[base + r * stride];
+__device__ __forceinline__ int brev(int t, int logn) {
+  return (int)(__brev((unsigned)t) >> (32 - logn));
+}
+
+// the twiddles exp(-2 pi i k / n), k < n/2, into LDS (one sincospi per thread)
+__device__ __forceinline__ void twiddles(double2* tw, int t, int n) {
   if (t < n / 2) {
     double sn, cs;
     sincospi(2.0 * t / n, &sn, &cs);
-    tw[t] = make_double2(cs, sign * sn);
+    tw[t] = make_double2(cs, -sn);
   }
-  __syncthreads();
+}
+
+// Radix-2 decimation in time over the n = blockDim.x threads of the block: on
+// entry thread t holds element brev(t) of the input, on return element t of
+// its transform (sign -1 forward, +1 with INV).  A butterfly's partner
+// t ^ half lies in the same wavefront for half < 64 and is exchanged with a
+// lane shuffle; the longer stages exchange through buf.  The stage of length
+// len uses the twiddle k = pos n / len.  Ends with buf free for reuse.
+template <bool INV>
+__device__ __forceinline__ double2 fft_stages(double2 v, int t, int n, const double2* tw,
+                                              double2* buf) {
   for (int len = 2; len <= n; len <<= 1) {
     const int half = len >> 1;
     double2 o;
@@ -143,7 +141,8 @@ __global__ __launch_bounds__(1024) void k_fft1d(double2* __restrict__ data, int 
       __syncthreads();
     }
     const int pos = t & (half - 1);
-    const double2 w = tw[pos * (n / len)];
+    double2 w = tw[pos * (n / len)];
+    if (INV) w.y = -w.y;
     // lower element t: a + w b with b = o; upper element: a - w b with a = o, b = v
     if ((t & half) == 0) {
       const double2 bb = cmul(o, w);
@@ -153,6 +152,33 @@ __global__ __launch_bounds__(1024) void k_fft1d(double2* __restrict__ data, int 
       v = make_double2(o.x - bb.x, o.y - bb.y);
     }
   }
+  return v;
+}
+
+// Blocks are dispatched round-robin to the 8 XCDs, each with its own L2.  A
+// column transform touches 16 bytes of every row, so the 8 columns that share
+// a 128-byte line are given to blocks on one XCD: block id -> transform index
+// with each XCD taking a contiguous range (nblocks a multiple of 8).
+__device__ __forceinline__ long long xcd_order(long long id, long long nblocks) {
+  if (nblocks & 7) return id;
+  return (id & 7) * (nblocks >> 3) + (id >> 3);
+}
+
+// transform b: elements at base(b) + j*stride, j = 0..n-1, where
+// base(b) = (b / inner) * outer + (b % inner) * istride; XCD-ordered when
+// the transforms are strided columns
+__global__ __launch_bounds__(1024) void k_fft1d(double2* __restrict__ data, int n, int logn,
+                                                long long stride, int inner, long long outer,
+                                                long long istride, double sign) {
+  __shared__ double2 buf[1024];
+  __shared__ double2 tw[512];
+  const long long b = stride == 1 ? (long long)blockIdx.x : xcd_order(blockIdx.x, gridDim.x);
+  const long long base = (b / inner) * outer + (b % inner) * istride;
+  const int t = threadIdx.x;
+  double2 v = data[base + brev(t, logn) * stride];
+  twiddles(tw, t, n);
+  __syncthreads();
+  v = sign > 0.0 ? fft_stages<true>(v, t, n, tw, buf) : fft_stages<false>(v, t, n, tw, buf);
   data[base + t * stride] = v;
 }
 
@@ -173,62 +199,87 @@ hipError_t fft2d(const KParams& p, double2* d, int nplanes, double sign, hipStre
 
 namespace {
 
-// complex planes: 0 = Ax + i Ay (bottom), 1 = Az (bottom), 2 = Ax + i Ay (top), 3 = Az (top)
-__global__ void k_pack_boundary_planes(const KParams p, const double* __restrict__ f,
-                                       double2* __restrict__ S) {
-  const long long sp = p.splane;
-  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < sp;
-       col += (long long)gridDim.x * blockDim.x) {
-    const long long ob = NG * sp + col, ot = (NG + p.nz - 1) * sp + col;
-    S[col] = make_double2(f[AX * p.sfield + ob], f[AY * p.sfield + ob]);
-    S[sp + col] = make_double2(f[AZ * p.sfield + ob], 0.0);
-    S[2 * sp + col] = make_double2(f[AX * p.sfield + ot], f[AY * p.sfield + ot]);
-    S[3 * sp + col] = make_double2(f[AZ * p.sfield + ot], 0.0);
-  }
+// The potential-field ghosts of A in three passes over the complex planes
+// q = 0: Ax + i Ay (bottom), 1: Az (bottom), 2: Ax + i Ay (top), 3: Az (top):
+//   rows     the boundary rows of f transformed along x into S[q];
+//   columns  each column of S[q] transformed along y, multiplied by the
+//            filter of ghost layer j and transformed back along y, into
+//            T[3q + j-1] (one forward and three inverse transforms per block);
+//   rows     each row of T transformed back along x and written into the
+//            ghost planes of f.
+// The inverse 2-D transform takes its columns first: the two 1-D passes
+// commute.
+
+__device__ __forceinline__ long long pf_plane(const KParams& p, int q) {
+  return (q < 2 ? NG : NG + p.nz - 1) * p.splane;
 }
 
-// T[q*3 + j-1] = S[q] * exp(-|k| d_qj) / (nx ny), d = -f_bot (z(0) - z(-j))
-// below (contrast grows with depth, Sect. 2.4) and d = z(nz-1+j) - z(nz-1)
-// above (eq. 17)
-__global__ void k_pf_filter(const KParams p, const double2* __restrict__ S,
-                            double2* __restrict__ T) {
+// block (q, row) of 4 * ny, nx threads
+__global__ __launch_bounds__(1024) void k_pf_rows_fwd(const KParams p,
+                                                      const double* __restrict__ f,
+                                                      double2* __restrict__ S) {
+  __shared__ double2 buf[1024];
+  __shared__ double2 tw[512];
+  const int q = blockIdx.x / p.ny, row = blockIdx.x - q * p.ny;
+  const int t = threadIdx.x, n = p.nx;
+  const long long c = pf_plane(p, q) + (long long)row * n + brev(t, ilog2(n));
+  const double2 v = (q & 1) ? make_double2(f[AZ * p.sfield + c], 0.0)
+                            : make_double2(f[AX * p.sfield + c], f[AY * p.sfield + c]);
+  twiddles(tw, t, n);
+  __syncthreads();
+  S[q * p.splane + (long long)row * n + t] = fft_stages<false>(v, t, n, tw, buf);
+}
+
+// T[3q + j-1] = S[q] exp(-|k| d_qj) / (nx ny) along each column, with
+// d = -f_bot (z(0) - z(-j)) below (the contrast grows with depth, Sect. 2.4)
+// and d = z(nz-1+j) - z(nz-1) above (eq. 17).  Block (q, column) of 4 * nx,
+// XCD-ordered, ny threads.
+__global__ __launch_bounds__(1024) void k_pf_columns(const KParams p,
+                                                     const double2* __restrict__ S,
+                                                     double2* __restrict__ T) {
+  __shared__ double2 buf[1024];
+  __shared__ double2 tw[512];
+  const int b = int(xcd_order(blockIdx.x, gridDim.x));
+  const int q = b / p.nx, col = b - q * p.nx;
+  const int t = threadIdx.x, n = p.ny, logn = ilog2(n);
   const long long sp = p.splane;
+  const double2 v0 = S[q * sp + (long long)brev(t, logn) * p.nx + col];
+  twiddles(tw, t, n);
+  __syncthreads();
+  const double2 v = fft_stages<false>(v0, t, n, tw, buf);
+  const double k = kabs(p, col, t);
+  const double* dist = p.pf_dist[q < 2 ? 0 : 1];
   const double inv_n = 1.0 / double(sp);
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < 4 * sp;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int q = int(i / sp);
-    const long long col = i - q * sp;
-    const int iy = int(col / p.nx), ix = int(col - (long long)iy * p.nx);
-    const double k = kabs(p, ix, iy);
-    const double2 v = S[i];
-    const double* dist = p.pf_dist[q < 2 ? 0 : 1];
-#pragma unroll
-    for (int j = 1; j <= NG; ++j) {
-      const double fac = exp(-k * dist[j - 1]) * inv_n;
-      T[(q * NG + j - 1) * sp + col] = make_double2(v.x * fac, v.y * fac);
-    }
+  for (int j = 0; j < NG; ++j) {
+    const double fac = exp(-k * dist[j]) * inv_n;
+    buf[t] = make_double2(v.x * fac, v.y * fac);
+    __syncthreads();
+    const double2 u = buf[brev(t, logn)];
+    __syncthreads();
+    T[(q * NG + j) * sp + (long long)t * p.nx + col] = fft_stages<true>(u, t, n, tw, buf);
   }
 }
 
-__global__ void k_unpack_boundary_planes(const KParams p, const double2* __restrict__ T,
-                                         double* __restrict__ f) {
-  const long long sp = p.splane;
-  for (long long col = blockIdx.x * (long long)blockDim.x + threadIdx.x; col < sp;
-       col += (long long)gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int j = 1; j <= NG; ++j) {
-      const long long ob = (NG - j) * sp + col, ot = (NG + p.nz - 1 + j) * sp + col;
-      const double2 bxy = T[(0 * NG + j - 1) * sp + col];
-      const double2 bz = T[(1 * NG + j - 1) * sp + col];
-      const double2 txy = T[(2 * NG + j - 1) * sp + col];
-      const double2 tz = T[(3 * NG + j - 1) * sp + col];
-      f[AX * p.sfield + ob] = bxy.x;
-      f[AY * p.sfield + ob] = bxy.y;
-      f[AZ * p.sfield + ob] = bz.x;
-      f[AX * p.sfield + ot] = txy.x;
-      f[AY * p.sfield + ot] = txy.y;
-      f[AZ * p.sfield + ot] = tz.x;
-    }
+// block (3q + j-1, row) of 12 * ny, nx threads: ghost layer j below (q < 2)
+// or above
+__global__ __launch_bounds__(1024) void k_pf_rows_inv(const KParams p,
+                                                      const double2* __restrict__ T,
+                                                      double* __restrict__ f) {
+  __shared__ double2 buf[1024];
+  __shared__ double2 tw[512];
+  const int qj = blockIdx.x / p.ny, row = blockIdx.x - qj * p.ny;
+  const int q = qj / NG, j = qj - q * NG + 1;
+  const int t = threadIdx.x, n = p.nx;
+  const double2 u = T[qj * p.splane + (long long)row * n + brev(t, ilog2(n))];
+  twiddles(tw, t, n);
+  __syncthreads();
+  const double2 v = fft_stages<true>(u, t, n, tw, buf);
+  const long long o = (q < 2 ? NG - j : NG + p.nz - 1 + j) * p.splane + (long long)row * n + t;
+  if (q & 1) {
+    f[AZ * p.sfield + o] = v.x;
+  } else {
+    f[AX * p.sfield + o] = v.x;
+    f[AY * p.sfield + o] = v.y;
   }
 }
 
@@ -502,14 +553,9 @@ hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch
                                    hipStream_t s) {
   double2* S = scratch;                 // 4 planes
   double2* T = scratch + 4 * p.splane;  // 12 planes
-  hipLaunchKernelGGL(k_pack_boundary_planes, dim3(grid_for(p.splane)), dim3(256), 0, s, p, f, S);
-  hipError_t e = fft2d(p, S, 4, -1.0, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pf_filter, dim3(grid_for(4 * p.splane)), dim3(256), 0, s, p, S, T);
-  e = fft2d(p, T, 4 * NG, +1.0, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unpack_boundary_planes, dim3(grid_for(p.splane)), dim3(256), 0, s, p, T,
-                     f);
+  hipLaunchKernelGGL(k_pf_rows_fwd, dim3(4 * p.ny), dim3(p.nx), 0, s, p, f, S);
+  hipLaunchKernelGGL(k_pf_columns, dim3(4 * p.nx), dim3(p.ny), 0, s, p, S, T);
+  hipLaunchKernelGGL(k_pf_rows_inv, dim3(4 * NG * p.ny), dim3(p.nx), 0, s, p, T, f);
   return hipGetLastError();
 }
 

@@ -355,6 +355,11 @@ __device__ __forceinline__ void window_loop(Smem<Real, NEWTON>& sm, const double
     constexpr int r = decltype(rc)::value;
     double c1, c2, c3;
     zmetric(p, k, c1, c2, c3);
+    // the metric's scalar loads waited for here, once: a wait inside the
+    // exec-masked stores below would also drain the LDS stores before it
+    c1 = sreg(c1);
+    c2 = sreg(c2);
+    c3 = sreg(c3);
 #pragma unroll
     for (int fi = 0; fi < NF; ++fi) {
       const double q0 = w[fi][r % 7], q1 = w[fi][(r + 1) % 7], q2 = w[fi][(r + 2) % 7];
