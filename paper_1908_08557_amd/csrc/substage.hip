@@ -353,6 +353,11 @@ __device__ __forceinline__ void window_loop(Smem<Real, NEWTON>& sm, const double
 
   auto plane = [&](auto rc, int k) {
     constexpr int r = decltype(rc)::value;
+    // W is the critical path of the plane; the update of the previous plane
+    // shares the SIMDs with it and has slack, so the window issues first
+    // until the plane is staged (the arbiter otherwise favours the older
+    // right-hand-side waves)
+    __builtin_amdgcn_s_setprio(2);
     double c1, c2, c3;
     zmetric(p, k, c1, c2, c3);
     // the metric's scalar loads waited for here, once: a wait inside the
@@ -374,6 +379,7 @@ __device__ __forceinline__ void window_loop(Smem<Real, NEWTON>& sm, const double
       if (wown) sm.ZZ[fi][wo] = Real(s2 * c2 + s1 * c3);
     }
     lds_barrier();   // B1: the plane is staged
+    __builtin_amdgcn_s_setprio(0);
     // the stencils while the slot of plane k-3 is free, then the next
     // plane's values into it (consumed at the next plane; the last plane
     // reloads a plane it already holds: the load is unconditional)
