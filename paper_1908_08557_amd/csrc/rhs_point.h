@@ -143,25 +143,39 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   for (int c = 0; c < 3; ++c) {
     S g[3], h[6];
     src.gh(AX + c, g, h);
-    // 0/1 weights of this component (uniform across the wave): the
-    // accumulations are multiply-adds by them, which add exact zeros to the
-    // entries the component does not reach (no per-lane selects in a rolled
-    // loop)
-    const S e0 = S(c == 0 ? 1.0 : 0.0), e1 = S(c == 1 ? 1.0 : 0.0), e2 = S(c == 2 ? 1.0 : 0.0);
-    divA = divA + (g[0] * e0 + g[1] * e1 + g[2] * e2);
-    B[0] = B[0] + (g[1] * e2 - g[2] * e1);
-    B[1] = B[1] + (g[2] * e0 - g[0] * e2);
-    B[2] = B[2] + (g[0] * e1 - g[1] * e0);
+    // the entries component c reaches (c is uniform across the wave: scalar
+    // branches, and no arithmetic on the entries it does not reach)
     const S lap = h[0] + h[1] + h[2];
-    lapA[0] = lapA[0] + lap * e0;
-    lapA[1] = lapA[1] + lap * e1;
-    lapA[2] = lapA[2] + lap * e2;
+    if (c == 0) {
+      divA = divA + g[0];
+      B[1] = B[1] + g[2];
+      B[2] = B[2] - g[1];
+      lapA[0] = lap;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const S hj0 = h[hslot(j, 0)], hj1 = h[hslot(j, 1)], hj2 = h[hslot(j, 2)];
-      dB[0][j] = dB[0][j] + (hj1 * e2 - hj2 * e1);
-      dB[1][j] = dB[1][j] + (hj2 * e0 - hj0 * e2);
-      dB[2][j] = dB[2][j] + (hj0 * e1 - hj1 * e0);
+      for (int j = 0; j < 3; ++j) {
+        dB[1][j] = dB[1][j] + h[hslot(j, 2)];
+        dB[2][j] = dB[2][j] - h[hslot(j, 1)];
+      }
+    } else if (c == 1) {
+      divA = divA + g[1];
+      B[0] = B[0] - g[2];
+      B[2] = B[2] + g[0];
+      lapA[1] = lap;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        dB[0][j] = dB[0][j] - h[hslot(j, 2)];
+        dB[2][j] = dB[2][j] + h[hslot(j, 0)];
+      }
+    } else {
+      divA = divA + g[2];
+      B[0] = B[0] + g[1];
+      B[1] = B[1] - g[0];
+      lapA[2] = lap;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        dB[0][j] = dB[0][j] + h[hslot(j, 1)];
+        dB[1][j] = dB[1][j] - h[hslot(j, 0)];
+      }
     }
   }
 #pragma unroll
@@ -407,37 +421,47 @@ __device__ __forceinline__ void rhs_momentum(const Src& src, const KParams& p,
   for (int c = 0; c < 3; ++c) {
     S g[3], h[6];
     src.gh(UX + c, g, h);   // g[j] = a_cj
-    // advection, the Laplacian of u_c and sum_j a_cj G_j (into mom[c], with
-    // selects so that a rolled loop indexes no register array)
+    // advection, the Laplacian of u_c and sum_j a_cj G_j (into mom[c])
     const S own = -(u[0] * g[0] + u[1] * g[1] + u[2] * g[2]) +
                   S(p.nu) * (h[0] + h[1] + h[2] + g[0] * Glr[0] + g[1] * Glr[1] + g[2] * Glr[2]);
-    // 0/1 weights of this component (uniform across the wave), as in
-    // rhs_magnetic: multiply-adds instead of per-lane selects
-    const S e0 = S(c == 0 ? 1.0 : 0.0), e1 = S(c == 1 ? 1.0 : 0.0), e2 = S(c == 2 ? 1.0 : 0.0);
-    mom[0] = mom[0] + own * e0;
-    mom[1] = mom[1] + own * e1;
-    mom[2] = mom[2] + own * e2;
-    // grad div u: d_i d_c u_c (Hessian column c), and a_ci G_c into component i
-    const S Gc = Glr[0] * e0 + Glr[1] * e1 + Glr[2] * e2;
-    const S hc[3] = {h[0] * e0 + h[3] * e1 + h[4] * e2,
-                     h[3] * e0 + h[1] * e1 + h[5] * e2,
-                     h[4] * e0 + h[5] * e1 + h[2] * e2};
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      mom[i] = mom[i] + S(p.nu) * (hc[i] * S(1.0 / 3.0) + g[i] * Gc);
-    divu = divu + (g[0] * e0 + g[1] * e1 + g[2] * e2);
+    // the component's own entries (c is uniform across the wave: scalar
+    // branches): own into mom[c], div u, G_c = d_c ln rho, the c-th Hessian
+    // column hc for grad div u, and a_ij a_ji (the diagonal now, the
+    // off-diagonal pairs as their second member arrives)
+    S Gc, hc[3];
     sq = sq + (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    // a_ij a_ji: the diagonal now, the off-diagonal pairs as their second member arrives
     if (c == 0) {
+      mom[0] = mom[0] + own;
+      divu = divu + g[0];
+      Gc = Glr[0];
+      hc[0] = h[0];
+      hc[1] = h[3];
+      hc[2] = h[4];
       cross = cross + g[0] * g[0];
       a01 = g[1];
       a02 = g[2];
     } else if (c == 1) {
+      mom[1] = mom[1] + own;
+      divu = divu + g[1];
+      Gc = Glr[1];
+      hc[0] = h[3];
+      hc[1] = h[1];
+      hc[2] = h[5];
       cross = cross + g[1] * g[1] + S(2.0) * g[0] * a01;
       a12 = g[2];
     } else {
+      mom[2] = mom[2] + own;
+      divu = divu + g[2];
+      Gc = Glr[2];
+      hc[0] = h[4];
+      hc[1] = h[5];
+      hc[2] = h[2];
       cross = cross + g[2] * g[2] + S(2.0) * (g[0] * a02 + g[1] * a12);
     }
+    // grad div u (d_i d_c u_c) and a_ci G_c into component i
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      mom[i] = mom[i] + S(p.nu) * (hc[i] * S(1.0 / 3.0) + g[i] * Gc);
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
