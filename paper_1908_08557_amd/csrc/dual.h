@@ -32,6 +32,7 @@ __device__ __forceinline__ Dual s_sqrt(Dual a) {
   const double r = sqrt(a.v);
   return Dual(r, a.d / (2.0 * r));
 }
+__device__ __forceinline__ Dual s_rsqrt(Dual a) { return Dual(1.0) / s_sqrt(a); }
 __device__ __forceinline__ Dual s_sin(Dual a) { return Dual(sin(a.v), cos(a.v) * a.d); }
 __device__ __forceinline__ double value_of(Dual a) { return a.v; }
 

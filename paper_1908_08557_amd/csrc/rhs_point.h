@@ -66,6 +66,17 @@ __device__ inline double s_exp(double a) { return exp(a); }
 __device__ inline float s_exp(float a) { return expf(a); }
 __device__ inline double s_sqrt(double a) { return sqrt(a); }
 __device__ inline float s_sqrt(float a) { return __fsqrt_rn(a); }
+// 1/sqrt(a), a > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y + y (1 - a y^2) / 2 (each at least doubles the correct bits;
+// the result is within a few units in the last place, not correctly rounded)
+__device__ inline double s_rsqrt(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double e = fma(-a * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-a * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ inline float s_rsqrt(float a) { return 1.0f / __fsqrt_rn(a); }
 __device__ inline double s_sin(double a) { return sin(a); }
 __device__ inline double value_of(double a) { return a; }
 
@@ -193,8 +204,7 @@ __device__ __forceinline__ void rhs_magnetic(const Src& src, const PointCtx<S>& 
   S b[3] = {S(0.0), S(0.0), S(0.0)}, iBn = S(0.0), vv[3] = {S(0.0), S(0.0), S(0.0)};
   S sbb = S(0.0);
   if (p.kappa0 != 0.0) {
-    const S Bn = s_sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2] + S(p.B_floor2));
-    iBn = S(1.0) / Bn;
+    iBn = s_rsqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2] + S(p.B_floor2));
 #pragma unroll
     for (int i = 0; i < 3; ++i) b[i] = B[i] * iBn;
 #pragma unroll
@@ -290,7 +300,8 @@ __device__ __forceinline__ S rhs_heating(const Src& src, const PointCtx<S>& pc,
       if constexpr (kFloat) {
         kc = float(p.kappa0 * exp(2.5 * src.v64(LT) - src.v64(LR)) * p.inv_cv);   // FP64 coefficient
       } else {
-        kc = S(p.kappa0) * s_exp(S(2.5) * src.v(LT) - src.v(LR)) * S(p.inv_cv);
+        // T^{5/2} / rho from the T and 1/rho of the zone (no further exp)
+        kc = S(p.kappa0) * (pv.T * pv.T * pv.T * s_rsqrt(pv.T)) * pv.irho * S(p.inv_cv);
       }
       e = e + kc * bracket;
     }
