@@ -1,4 +1,5 @@
-"""The Fourier boundary work at the benchmark's plane sizes: the ghost fill
+"""The Fourier boundary work at the benchmark's plane sizes (and two small
+unequal ones): the ghost fill
 (periodic x/y ghosts, the potential-field top and inverted potential-field
 bottom of eq. (17), the fixed photospheric density) and A_h* from B_z
 (eq. 7) on 512 x 512 and 1024 x 1024 planes, the largest transforms the
@@ -13,7 +14,9 @@ from parity_util import NG, perturbed
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(32, 16), (512, 512), (1024, 1024)]
+# (32, 16) and (16, 32): both transform lengths below one wavefront and
+# unequal, rows and columns of different length
+SIZES = [(32, 16), (16, 32), (512, 512), (1024, 1024)]
 DZ = 50.0 / 255      # the z spacing of the 512^2 x 256 and 1024^2 x 256 boxes
 
 
