@@ -116,6 +116,13 @@ def run_gpu(w, precision, steps, warmup, drivers):
     kms, nl = s.profile_read("substage")
     gms, ng_ = s.profile_read("ghosts")
     s.profile(False)
+    # the optional CFL selection of dt (outside the timed steps, which take dt
+    # as given): one call = one read pass with x/y/z stencils of A, the
+    # three maxima and their copy to the host
+    t1 = time.perf_counter()
+    for _ in range(5):
+        s.cfl_dt(st)
+    cfl_ms = 1e3 * (time.perf_counter() - t1) / 5
     finite = s.check_finite(st)
     s.close()
     del st
@@ -132,7 +139,7 @@ def run_gpu(w, precision, steps, warmup, drivers):
     return dict(value=zones / (elapsed / steps), ms_per_step=ms_step, dt=dt, finite=finite,
                 ms_per_step_blocks=blocks, ms_per_step_median_block=float(np.median(blocks)),
                 kernel_ms_per_launch=kernel_ms_per_launch, launches=nl,
-                ghosts_ms=ghosts_ms, substage_ms=substage_ms,
+                ghosts_ms=ghosts_ms, substage_ms=substage_ms, cfl_dt_ms=cfl_ms,
                 achieved_GBs=achieved, frac=achieved / HBM_PEAK_GBS,
                 step_GBs=BYTES_PER_ZONE_STEP * zones / (elapsed / steps) / 1e9)
 
@@ -470,6 +477,8 @@ def main():
                      # the whole step (three substages and their boundary
                      # work) against the same 640 B per zone
                      "step_GBs": r["step_GBs"], "step_frac": r["step_GBs"] / HBM_PEAK_GBS},
+        # dt by the CFL condition (cmhd_rk3_step with dt <= 0 adds this per step)
+        "cfl_dt_ms": r["cfl_dt_ms"],
     }
     if "fp32_split" in res and main_prec == "fp64":
         s = res["fp32_split"]
