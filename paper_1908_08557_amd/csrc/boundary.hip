@@ -16,9 +16,11 @@
 // Periodic mode: plane copies.
 //
 // Fourier transforms: radix-2 decimation-in-time, one workgroup per 1-D
-// transform staged in LDS (rows, then columns), float64 throughout.
-// Forward transform unnormalised, inverse normalised by 1/(nx ny) in the
-// spectral filter.  Because the multipliers are real and even in k, two real
+// transform staged in LDS, float64 throughout; the potential-field ghosts in
+// three fused passes (rows forward; per column forward, filter, inverse;
+// rows inverse), the other 2-D transforms as rows then columns.  Forward
+// transform unnormalised, inverse normalised by 1/(nx ny) in the spectral
+// filter.  Because the multipliers are real and even in k, two real
 // planes are filtered at once as the real and imaginary parts of one complex
 // plane.
 #include "launch.h"
