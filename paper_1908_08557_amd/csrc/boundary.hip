@@ -157,6 +157,45 @@ __device__ __forceinline__ double2 fft_stages(double2 v, int t, int n, const dou
   return v;
 }
 
+// The same stages for NG transforms of one block in lockstep (element t of
+// each in thread t): one barrier pair and one twiddle read per stage serve
+// all of them.  buf holds NG * n elements.
+template <bool INV>
+__device__ __forceinline__ void fft_stages3(double2 (&v)[NG], int t, int n, const double2* tw,
+                                            double2* buf) {
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1;
+    double2 o[NG];
+    if (half < 64) {
+#pragma unroll
+      for (int m = 0; m < NG; ++m) {
+        o[m].x = __shfl_xor(v[m].x, half);
+        o[m].y = __shfl_xor(v[m].y, half);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < NG; ++m) buf[m * n + t] = v[m];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < NG; ++m) o[m] = buf[m * n + (t ^ half)];
+      __syncthreads();
+    }
+    const int pos = t & (half - 1);
+    double2 w = tw[pos * (n / len)];
+    if (INV) w.y = -w.y;
+#pragma unroll
+    for (int m = 0; m < NG; ++m) {
+      if ((t & half) == 0) {
+        const double2 bb = cmul(o[m], w);
+        v[m] = make_double2(v[m].x + bb.x, v[m].y + bb.y);
+      } else {
+        const double2 bb = cmul(v[m], w);
+        v[m] = make_double2(o[m].x - bb.x, o[m].y - bb.y);
+      }
+    }
+  }
+}
+
 // Blocks are dispatched round-robin to the 8 XCDs, each with its own L2.  A
 // column transform touches 16 bytes of every row, so the 8 columns that share
 // a 128-byte line are given to blocks on one XCD: block id -> transform index
@@ -206,9 +245,10 @@ namespace {
 //   rows     the boundary rows of f transformed along x into S[q];
 //   columns  each column of S[q] transformed along y, multiplied by the
 //            filter of ghost layer j and transformed back along y, into
-//            T[3q + j-1] (one forward and three inverse transforms per block);
-//   rows     each row of T transformed back along x and written into the
-//            ghost planes of f.
+//            T[3q + j-1] (one forward and three inverse transforms per block,
+//            the three in lockstep);
+//   rows     the three rows of T[3q .. 3q+2] at one row index transformed
+//            back along x in lockstep and written into the ghost planes of f.
 // The inverse 2-D transform takes its columns first: the two 1-D passes
 // commute.
 
@@ -239,8 +279,9 @@ __global__ __launch_bounds__(1024) void k_pf_rows_fwd(const KParams p,
 __global__ __launch_bounds__(1024) void k_pf_columns(const KParams p,
                                                      const double2* __restrict__ S,
                                                      double2* __restrict__ T) {
-  __shared__ double2 buf[1024];
-  __shared__ double2 tw[512];
+  extern __shared__ double2 dyn[];   // [NG * n] exchange | [n/2] twiddles
+  double2* buf = dyn;
+  double2* tw = dyn + NG * p.ny;
   const int b = int(xcd_order(blockIdx.x, gridDim.x));
   const int q = b / p.nx, col = b - q * p.nx;
   const int t = threadIdx.x, n = p.ny, logn = ilog2(n);
@@ -252,36 +293,48 @@ __global__ __launch_bounds__(1024) void k_pf_columns(const KParams p,
   const double k = kabs(p, col, t);
   const double* dist = p.pf_dist[q < 2 ? 0 : 1];
   const double inv_n = 1.0 / double(sp);
+  double2 u[NG];
+#pragma unroll
   for (int j = 0; j < NG; ++j) {
     const double fac = exp(-k * dist[j]) * inv_n;
-    buf[t] = make_double2(v.x * fac, v.y * fac);
-    __syncthreads();
-    const double2 u = buf[brev(t, logn)];
-    __syncthreads();
-    T[(q * NG + j) * sp + (long long)t * p.nx + col] = fft_stages<true>(u, t, n, tw, buf);
+    buf[j * n + t] = make_double2(v.x * fac, v.y * fac);
   }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NG; ++j) u[j] = buf[j * n + brev(t, logn)];
+  __syncthreads();
+  fft_stages3<true>(u, t, n, tw, buf);
+#pragma unroll
+  for (int j = 0; j < NG; ++j) T[(q * NG + j) * sp + (long long)t * p.nx + col] = u[j];
 }
 
-// block (3q + j-1, row) of 12 * ny, nx threads: ghost layer j below (q < 2)
-// or above
+// block (q, row) of 4 * ny, nx threads: the three ghost layers j = 1..3
+// below (q < 2) or above, transformed in lockstep
 __global__ __launch_bounds__(1024) void k_pf_rows_inv(const KParams p,
                                                       const double2* __restrict__ T,
                                                       double* __restrict__ f) {
-  __shared__ double2 buf[1024];
-  __shared__ double2 tw[512];
-  const int qj = blockIdx.x / p.ny, row = blockIdx.x - qj * p.ny;
-  const int q = qj / NG, j = qj - q * NG + 1;
+  extern __shared__ double2 dyn[];   // [NG * n] exchange | [n/2] twiddles
+  double2* buf = dyn;
+  double2* tw = dyn + NG * p.nx;
+  const int q = blockIdx.x / p.ny, row = blockIdx.x - q * p.ny;
   const int t = threadIdx.x, n = p.nx;
-  const double2 u = T[qj * p.splane + (long long)row * n + brev(t, ilog2(n))];
+  const long long c = (long long)row * n + brev(t, ilog2(n));
+  double2 u[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) u[j] = T[(q * NG + j) * p.splane + c];
   twiddles(tw, t, n);
   __syncthreads();
-  const double2 v = fft_stages<true>(u, t, n, tw, buf);
-  const long long o = (q < 2 ? NG - j : NG + p.nz - 1 + j) * p.splane + (long long)row * n + t;
-  if (q & 1) {
-    f[AZ * p.sfield + o] = v.x;
-  } else {
-    f[AX * p.sfield + o] = v.x;
-    f[AY * p.sfield + o] = v.y;
+  fft_stages3<true>(u, t, n, tw, buf);
+#pragma unroll
+  for (int j = 1; j <= NG; ++j) {
+    const long long o =
+        (q < 2 ? NG - j : NG + p.nz - 1 + j) * p.splane + (long long)row * n + t;
+    if (q & 1) {
+      f[AZ * p.sfield + o] = u[j - 1].x;
+    } else {
+      f[AX * p.sfield + o] = u[j - 1].x;
+      f[AY * p.sfield + o] = u[j - 1].y;
+    }
   }
 }
 
@@ -556,8 +609,10 @@ hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch
   double2* S = scratch;                 // 4 planes
   double2* T = scratch + 4 * p.splane;  // 12 planes
   hipLaunchKernelGGL(k_pf_rows_fwd, dim3(4 * p.ny), dim3(p.nx), 0, s, p, f, S);
-  hipLaunchKernelGGL(k_pf_columns, dim3(4 * p.nx), dim3(p.ny), 0, s, p, S, T);
-  hipLaunchKernelGGL(k_pf_rows_inv, dim3(4 * NG * p.ny), dim3(p.nx), 0, s, p, T, f);
+  hipLaunchKernelGGL(k_pf_columns, dim3(4 * p.nx), dim3(p.ny),
+                     (NG * p.ny + p.ny / 2) * sizeof(double2), s, p, S, T);
+  hipLaunchKernelGGL(k_pf_rows_inv, dim3(4 * p.ny), dim3(p.nx),
+                     (NG * p.nx + p.nx / 2) * sizeof(double2), s, p, T, f);
   return hipGetLastError();
 }
 
