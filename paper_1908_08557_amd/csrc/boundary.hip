@@ -157,34 +157,34 @@ __device__ __forceinline__ double2 fft_stages(double2 v, int t, int n, const dou
   return v;
 }
 
-// The same stages for NG transforms of one block in lockstep (element t of
+// The same stages for M transforms of one block in lockstep (element t of
 // each in thread t): one barrier pair and one twiddle read per stage serve
-// all of them.  buf holds NG * n elements.
-template <bool INV>
-__device__ __forceinline__ void fft_stages3(double2 (&v)[NG], int t, int n, const double2* tw,
-                                            double2* buf) {
+// all of them.  buf holds M * n elements.
+template <bool INV, int M>
+__device__ __forceinline__ void fft_stages_m(double2 (&v)[M], int t, int n, const double2* tw,
+                                             double2* buf) {
   for (int len = 2; len <= n; len <<= 1) {
     const int half = len >> 1;
-    double2 o[NG];
+    double2 o[M];
     if (half < 64) {
 #pragma unroll
-      for (int m = 0; m < NG; ++m) {
+      for (int m = 0; m < M; ++m) {
         o[m].x = __shfl_xor(v[m].x, half);
         o[m].y = __shfl_xor(v[m].y, half);
       }
     } else {
 #pragma unroll
-      for (int m = 0; m < NG; ++m) buf[m * n + t] = v[m];
+      for (int m = 0; m < M; ++m) buf[m * n + t] = v[m];
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < NG; ++m) o[m] = buf[m * n + (t ^ half)];
+      for (int m = 0; m < M; ++m) o[m] = buf[m * n + (t ^ half)];
       __syncthreads();
     }
     const int pos = t & (half - 1);
     double2 w = tw[pos * (n / len)];
     if (INV) w.y = -w.y;
 #pragma unroll
-    for (int m = 0; m < NG; ++m) {
+    for (int m = 0; m < M; ++m) {
       if ((t & half) == 0) {
         const double2 bb = cmul(o[m], w);
         v[m] = make_double2(v[m].x + bb.x, v[m].y + bb.y);
@@ -242,7 +242,8 @@ namespace {
 
 // The potential-field ghosts of A in three passes over the complex planes
 // q = 0: Ax + i Ay (bottom), 1: Az (bottom), 2: Ax + i Ay (top), 3: Az (top):
-//   rows     the boundary rows of f transformed along x into S[q];
+//   rows     the boundary rows of f transformed along x into S[q] (the two
+//            planes of one boundary and row index in lockstep);
 //   columns  each column of S[q] transformed along y, multiplied by the
 //            filter of ghost layer j and transformed back along y, into
 //            T[3q + j-1] (one forward and three inverse transforms per block,
@@ -256,20 +257,25 @@ __device__ __forceinline__ long long pf_plane(const KParams& p, int q) {
   return (q < 2 ? NG : NG + p.nz - 1) * p.splane;
 }
 
-// block (q, row) of 4 * ny, nx threads
+// block (boundary, row) of 2 * ny, nx threads: the two planes q = 2 side,
+// 2 side + 1 (A_x + i A_y and A_z of the bottom or top plane) of one row
+// index in lockstep
 __global__ __launch_bounds__(1024) void k_pf_rows_fwd(const KParams p,
                                                       const double* __restrict__ f,
                                                       double2* __restrict__ S) {
-  __shared__ double2 buf[1024];
-  __shared__ double2 tw[512];
-  const int q = blockIdx.x / p.ny, row = blockIdx.x - q * p.ny;
+  extern __shared__ double2 dyn[];   // [2 * n] exchange | [n/2] twiddles
+  double2* buf = dyn;
+  double2* tw = dyn + 2 * p.nx;
+  const int side = blockIdx.x / p.ny, row = blockIdx.x - side * p.ny;
   const int t = threadIdx.x, n = p.nx;
-  const long long c = pf_plane(p, q) + (long long)row * n + brev(t, ilog2(n));
-  const double2 v = (q & 1) ? make_double2(f[AZ * p.sfield + c], 0.0)
-                            : make_double2(f[AX * p.sfield + c], f[AY * p.sfield + c]);
+  const long long o = pf_plane(p, 2 * side) + (long long)row * n + brev(t, ilog2(n));
+  double2 v[2] = {make_double2(f[AX * p.sfield + o], f[AY * p.sfield + o]),
+                  make_double2(f[AZ * p.sfield + o], 0.0)};
   twiddles(tw, t, n);
   __syncthreads();
-  S[q * p.splane + (long long)row * n + t] = fft_stages<false>(v, t, n, tw, buf);
+  fft_stages_m<false, 2>(v, t, n, tw, buf);
+#pragma unroll
+  for (int m = 0; m < 2; ++m) S[(2 * side + m) * p.splane + (long long)row * n + t] = v[m];
 }
 
 // T[3q + j-1] = S[q] exp(-|k| d_qj) / (nx ny) along each column, with
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_pf_columns(const KParams p,
 #pragma unroll
   for (int j = 0; j < NG; ++j) u[j] = buf[j * n + brev(t, logn)];
   __syncthreads();
-  fft_stages3<true>(u, t, n, tw, buf);
+  fft_stages_m<true, NG>(u, t, n, tw, buf);
 #pragma unroll
   for (int j = 0; j < NG; ++j) T[(q * NG + j) * sp + (long long)t * p.nx + col] = u[j];
 }
@@ -324,7 +330,7 @@ __global__ __launch_bounds__(1024) void k_pf_rows_inv(const KParams p,
   for (int j = 0; j < NG; ++j) u[j] = T[(q * NG + j) * p.splane + c];
   twiddles(tw, t, n);
   __syncthreads();
-  fft_stages3<true>(u, t, n, tw, buf);
+  fft_stages_m<true, NG>(u, t, n, tw, buf);
 #pragma unroll
   for (int j = 1; j <= NG; ++j) {
     const long long o =
@@ -608,7 +614,8 @@ hipError_t launch_potential_ghosts(const KParams& p, double* f, double2* scratch
                                    hipStream_t s) {
   double2* S = scratch;                 // 4 planes
   double2* T = scratch + 4 * p.splane;  // 12 planes
-  hipLaunchKernelGGL(k_pf_rows_fwd, dim3(4 * p.ny), dim3(p.nx), 0, s, p, f, S);
+  hipLaunchKernelGGL(k_pf_rows_fwd, dim3(2 * p.ny), dim3(p.nx),
+                     (2 * p.nx + p.nx / 2) * sizeof(double2), s, p, f, S);
   hipLaunchKernelGGL(k_pf_columns, dim3(4 * p.nx), dim3(p.ny),
                      (NG * p.ny + p.ny / 2) * sizeof(double2), s, p, S, T);
   hipLaunchKernelGGL(k_pf_rows_inv, dim3(4 * p.ny), dim3(p.nx),
