@@ -48,6 +48,14 @@ CASES = {
     "strat32x32x24_norad": lambda: _norad(W.small_stratified(32, 32, 24)),
     "strat16x32x8": lambda: W.small_stratified(16, 32, 8, Lxy=8.0, z1=6.0, nbip=1),
     "strat64x16x12": lambda: W.small_stratified(64, 16, 12, Lxy=16.0, z1=10.0, nbip=2),
+    # the extreme plane shapes: 64 x 1 and 1 x 64 tiles (XCD patches one tile
+    # high or wide), transforms of length 1024 beside 16, one plane per z
+    # chunk; the z spacing of the 512^2 x 256 box, so that the inverted
+    # potential field below stays well conditioned at dx = 62.5 km
+    "strat1024x16x12": lambda: W.small_stratified(1024, 16, 12, Lxy=64.0, z1=11 * 50.0 / 255,
+                                                  nbip=2),
+    "strat16x1024x12": lambda: W.small_stratified(16, 1024, 12, Lxy=64.0, z1=11 * 50.0 / 255,
+                                                  nbip=2),
 }
 
 
